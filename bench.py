@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the APH predistorter forward apply on one MI355X.
+
+Workload (default): one stream of N = 2^24 complex64 OFDM-like samples (16-QAM
+on 1200 of 2048 subcarriers, RMS 0.25), odd orders {1,3,5,7} in the main and
+the conjugate branch, L = 4 taps, DC term; FP32 arithmetic.  One step = one
+forward apply of the whole stream (every step of Eq. 1 / Algorithm 1), on
+inputs already resident in HBM.  Input/output buffers rotate over >= 2 GiB so
+the 256 MB last-level cache cannot serve repeated steps.
+
+Prints ONE JSON line with the throughput, the HBM roofline of the kernel
+(algorithmic bytes / kernel time, timed with HIP events on the launch stream)
+and the FP64 oracle timed on the host (which also gates accuracy).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DPD Msamples/s + % HBM roofline at NMSE≤-110 dB vs oracle; grad-step time"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SAMPLE = 16          # 8 B complex64 read + 8 B written
+ROTATE_BYTES = 2 << 30
+PMC_FILE = os.path.join(ROOT, "profiles", "dpd_fwd_n2p24_P7_L4_traffic.json")
+KERNEL_SOURCES = ["paper_1612_09001_amd/csrc/dpd_fwd_kernels.h",
+                  "paper_1612_09001_amd/csrc/dpd_internal.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(n: int):
+    """HBM bytes per launch from committed rocprofv3 --pmc counters, scaled by
+    the same counters read on a plain copy of known size; null when the
+    kernel sources changed since the counters were taken."""
+    try:
+        with open(PMC_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash() or d.get("n") != n:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline(x_host, z_gpu, mo, co, L, h):
+    """FP64 oracle on the host cores over the same stream (the whole config-2
+    workload, median of 3); also gates the GPU output against it."""
+    import oracle
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from metrics import max_rel, nmse_db
+
+    orc = oracle.Oracle()
+    times = []
+    z = None
+    for _ in range(3):
+        t = time.perf_counter()
+        z = orc.forward(x_host, mo, co, L, h)
+        times.append(time.perf_counter() - t)
+    t = float(np.median(times))
+    n = x_host.size
+    acc = {"nmse_db": round(nmse_db(z_gpu, z), 2), "max_rel": float("%.3g" % max_rel(z_gpu, z))}
+    acc["pass"] = bool(acc["nmse_db"] <= -110.0 and acc["max_rel"] <= 2e-5)
+    base = {"value": round(n / t / 1e6, 3), "unit": "Msamples/s", "cores": orc.threads(),
+            "kind": "oracle",
+            "sample": "whole workload: %d samples, FP64 C oracle (gcc -O2, OpenMP), median of 3" % n}
+    return base, acc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--log2n", type=int, default=24)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
+    ap.add_argument("--tune", default="", help="S,LDS override, e.g. 4,1")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+              "(see DESIGN.md for how the path would shard)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1612_09001_amd import dpd, signals
+
+    n = 1 << args.log2n
+    mo = co = [1, 3, 5, 7]
+    L = 4
+    x_host = signals.ofdm_16qam(n, config_id=2)
+    h = signals.aph_coeffs(mo, co, L, config_id=2)
+    plan = dpd.Plan(mo, co, L, h)
+    if args.tune:
+        s, lds = (int(v) for v in args.tune.split(","))
+        plan.set_tune(samples_per_thread=s, stage_lds=lds)
+    tune = plan.get_tune()
+
+    nbuf = max(2, ROTATE_BYTES // (2 * 8 * n))
+    xs = [torch.from_numpy(x_host).cuda() for _ in range(nbuf)]
+    zs = [torch.empty_like(xs[0]) for _ in range(nbuf)]
+    stream = dpd.current_stream()
+    ptrs = [(a.data_ptr(), b.data_ptr()) for a, b in zip(xs, zs)]
+    handle = plan.handle
+
+    def step(i):
+        pi, po = ptrs[i % nbuf]
+        dpd.dpd_apply(handle, stream, pi, po, n)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record()
+        step(i)
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    kern_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    ms_per_step = wall * 1e3 / args.steps
+    value = n * args.steps / wall / 1e6
+    achieved = BYTES_PER_SAMPLE * n / (kern_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Msamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded OFDM-like 16-QAM, 1200/2048 subcarriers, RMS 0.25)",
+        "config": {"workload": "single stream N=2^%d complex64, orders {1,3,5,7} main+conj, "
+                               "L=4, DC term, FP32 forward apply" % args.log2n,
+                   "n": n, "L": L, "orders": mo, "tune": tune, "rotating_buffers": nbuf},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile(n),
+                     "kernel_ms": round(kern_ms, 5),
+                     "algorithmic_bytes_per_launch": BYTES_PER_SAMPLE * n},
+    }
+    if not args.no_cpu:
+        z_gpu = zs[(args.steps - 1) % nbuf].cpu().numpy()
+        base, acc = cpu_baseline(x_host, z_gpu, mo, co, L, h)
+        out["cpu_baseline"] = base
+        out["accuracy"] = acc
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

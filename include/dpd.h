@@ -1,0 +1,201 @@
+/*
+ * dpd.h -- C ABI of libdpd, an MI355X (gfx950) implementation of the
+ * augmented parallel Hammerstein (APH) digital predistorter of Li et al.,
+ * "Parallel Digital Predistortion Design on Mobile GPU and Embedded Multicore
+ * CPU for Mobile Transmitters".
+ *
+ * What the library computes (Eq. 1, section 2.1; Algorithm 1, section 3):
+ *
+ *   z_n = c + sum_{p in I_P} sum_{k=0}^{L-1} h_{p,k} psi_p(x_{n-k})
+ *           + sum_{q in I_Q} sum_{k=0}^{L-1} hbar_{q,k} conj(psi_q(x_{n-k})),
+ *   psi_p(x) = |x|^(p-1) x     (odd orders p, monomial basis),
+ *
+ * for n = 0..N-1, with x_m = 0 for m < 0 unless a history is carried.  The tap
+ * sum has L terms (k = 0..L-1), matching the L-entry coefficient vectors of
+ * section 2.2.  Arithmetic is IEEE FP32 with fused multiply-add.
+ *
+ * Conventions shared by every entry point
+ *   - Samples are interleaved complex64 (float re, float im; 8 bytes), in
+ *     device memory owned by the caller.  Pointers must be 8-byte aligned;
+ *     16-byte alignment (and an even row stride) selects the vector fast path.
+ *   - Coefficients use the stacking of section 2.2: for each main-branch order
+ *     (in the order passed to dpd_create) its L taps, then for each
+ *     conjugate-branch order its L taps, then c.  K = (n_main + n_conj)*L + 1
+ *     complex values, interleaved as 2K floats.
+ *   - Orders are odd, 1 <= p <= 15, strictly ascending within a branch; the
+ *     same order may appear in both branches.  1 <= L <= 16.
+ *   - A stream argument is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Device work is enqueued asynchronously on it; no call below
+ *     synchronizes the host unless it says so.
+ *   - Every call returns a dpd_status.  Nothing throws or aborts across the
+ *     ABI; out-parameters are left untouched on failure.  DPD_EHIP carries the
+ *     HIP error code in dpd_last_hip_error() (per host thread).  Kernel faults
+ *     surface at the caller's next synchronization.
+ *   - Input and output ranges must not overlap (later tiles read halo samples
+ *     that earlier tiles would already have overwritten): overlap is
+ *     DPD_EINVAL.
+ */
+#ifndef DPD_H
+#define DPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dpd_status {
+    DPD_OK = 0,
+    DPD_EINVAL = 1,        /* bad argument, null pointer, overlap, misalignment */
+    DPD_EUNSUPPORTED = 2,  /* order > 15, L > 16, or a size beyond the limits  */
+    DPD_ENOMEM = 3,        /* device or host allocation failed                 */
+    DPD_EHIP = 4           /* a HIP runtime call failed (dpd_last_hip_error)   */
+} dpd_status;
+
+typedef struct dpd_plan dpd_plan;
+typedef struct dpd_batch dpd_batch;
+
+/* Launch shape of the forward kernels; chosen by the autotuner or defaulted.
+ *   samples_per_thread: consecutive outputs per thread (2, 4 or 8)
+ *   stage_lds: 1 = the tile and its (L-1)-sample halo are staged through LDS
+ *              with coalesced 16-byte loads, 0 = each thread loads its own
+ *              window (halo re-reads hit the cache)
+ *   block: threads per block (fixed at 256 in this build)
+ *   grid_mult: persistent batched kernel only -- resident blocks per CU */
+typedef struct dpd_tune {
+    int32_t samples_per_thread;
+    int32_t stage_lds;
+    int32_t block;
+    int32_t grid_mult;
+} dpd_tune;
+
+/* ------------------------------------------------------------------ plans --
+ * dpd_create -- validate the order sets and L, copy the K host coefficients,
+ * precombine them into the device table the kernels read, and return a plan
+ * (section 2.1 basis and filters; section 2.2 coefficient stacking).
+ *   main_orders[n_main]  odd orders of the main branch, n_main >= 1
+ *   conj_orders[n_conj]  odd orders of the conjugate branch, n_conj >= 0
+ *                        (NULL allowed when n_conj == 0)
+ *   L                    taps per filter, 1..16
+ *   coeffs_host          2K floats (host memory), section 2.2 layout
+ *   out                  receives the plan; the caller frees it with
+ *                        dpd_destroy.  The plan owns its device table.
+ * Synchronous (device allocation + copy).  Uses the current HIP device. */
+dpd_status dpd_create(const int32_t *main_orders, int32_t n_main,
+                      const int32_t *conj_orders, int32_t n_conj, int32_t L,
+                      const float *coeffs_host, dpd_plan **out);
+
+/* dpd_destroy -- waits for the device, then frees the plan.  NULL is a no-op. */
+dpd_status dpd_destroy(dpd_plan *plan);
+
+/* dpd_num_coeffs -- K, the number of complex coefficients of the plan. */
+dpd_status dpd_num_coeffs(const dpd_plan *plan, int32_t *K);
+
+/* dpd_set_coeffs -- replace the coefficients from host memory (2K floats).
+ * Synchronous: waits for the device before overwriting the table. */
+dpd_status dpd_set_coeffs(dpd_plan *plan, const float *coeffs_host);
+
+/* dpd_set_coeffs_device -- replace the coefficients from device memory
+ * (K complex64), stream-ordered on `stream` with no host synchronization.
+ * Work on other streams that uses this plan must be ordered by the caller. */
+dpd_status dpd_set_coeffs_device(dpd_plan *plan, const void *coeffs_dev, void *stream);
+
+/* dpd_set_tune / dpd_get_tune -- launch shape of this plan's forward kernels.
+ * Fields outside the supported set are DPD_EINVAL. */
+dpd_status dpd_set_tune(dpd_plan *plan, const dpd_tune *tune);
+dpd_status dpd_get_tune(const dpd_plan *plan, dpd_tune *tune);
+
+/* ---------------------------------------------------------------- forward --
+ * dpd_apply -- Eq. (1) / Algorithm 1 on one stream of n samples with zero
+ * pre-history: out[t] = z_t for t = 0..n-1.  in, out: device complex64.
+ * n == 0 is a no-op returning DPD_OK. */
+dpd_status dpd_apply(dpd_plan *plan, void *stream, const void *in, void *out, int64_t n);
+
+/* dpd_apply_rows -- `rows` independent streams of n samples sharing the plan;
+ * row r starts at in + r*ld and out + r*ld (ld in samples, ld >= n).  The
+ * filter memory never crosses a row: every row starts from zero history. */
+dpd_status dpd_apply_rows(dpd_plan *plan, void *stream, const void *in, void *out,
+                          int64_t rows, int64_t n, int64_t ld);
+
+/* dpd_apply_coeffs -- as dpd_apply_rows, but the coefficients are read from a
+ * device array of K complex64 (section 2.2 layout) in stream order, without a
+ * host round trip (used by training).  The plan's own table is overwritten. */
+dpd_status dpd_apply_coeffs(dpd_plan *plan, void *stream, const void *coeffs_dev,
+                            const void *in, void *out, int64_t rows, int64_t n, int64_t ld);
+
+/* dpd_apply_hist -- streaming form: `hist` (device, L-1 complex64, oldest
+ * first) holds the inputs that precede in[0]; it is read, then overwritten
+ * with the last L-1 inputs of hist ++ in.  Calling it on consecutive chunks
+ * gives the same outputs as one call on the whole stream (the zero-filled
+ * pre-history of Eq. 2 is the special case hist = 0).  hist may be NULL only
+ * when L == 1. */
+dpd_status dpd_apply_hist(dpd_plan *plan, void *stream, const void *in, void *out, int64_t n,
+                          void *hist);
+
+/* --------------------------------------------------------------- backward --
+ * Gradient of a real loss E through Eq. (1) (not in the paper).  Complex
+ * gradients follow the convention dE/dRe + j dE/dIm (the one PyTorch uses).
+ *   coeffs_dev   K complex64 on the device, or NULL to use the plan's
+ *   x            inputs of the forward call, rows x n with row stride ld
+ *   grad_z       dE/dz for the outputs, same shape
+ *   grad_x       receives dE/dx (same shape), or NULL to skip it
+ *   grad_coeffs  receives dE/dcoeffs (K complex64, summed over all rows), or
+ *                NULL to skip it
+ *   ws, ws_bytes device workspace of at least dpd_backward_ws_size() bytes
+ * Deterministic: the same inputs give bitwise the same gradients.  Rows start
+ * from zero history. */
+dpd_status dpd_backward_ws_size(const dpd_plan *plan, int64_t rows, int64_t n, size_t *bytes);
+dpd_status dpd_backward(dpd_plan *plan, void *stream, const void *coeffs_dev, const void *x,
+                        const void *grad_z, void *grad_x, void *grad_coeffs, int64_t rows,
+                        int64_t n, int64_t ld, void *ws, size_t ws_bytes);
+
+/* ---------------------------------------------------------------- batched --
+ * Many streams of uneven length, each with its own order set, L and
+ * coefficients, in one persistent launch (many antennas of a massive-MIMO
+ * transmitter, section 1).  Orders are odd 1..P_max in both branches plus c,
+ * given as bit masks: bit b set <=> order 2b+1 present. */
+typedef struct dpd_stream_desc {
+    const void *in;          /* device complex64, n samples                  */
+    void *out;               /* device complex64, n samples                  */
+    int64_t n;               /* samples (>= 0)                               */
+    uint32_t main_mask;      /* main-branch orders (bit b <=> order 2b+1)    */
+    uint32_t conj_mask;      /* conjugate-branch orders                      */
+    int32_t L;               /* taps, 1..16                                  */
+    int32_t pad_;            /* zero                                         */
+    const void *coeffs_dev;  /* device, K complex64 in section 2.2 layout    */
+} dpd_stream_desc;
+
+/* dpd_batch_create -- validate the descriptors, build the tile table (tiles
+ * ordered most expensive first), upload it, and size the persistent grid.
+ * `tune` may be NULL for the default launch shape.  The descriptor pointers
+ * must stay valid for the life of the batch.  Synchronous. */
+dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_streams, const dpd_tune *tune,
+                            dpd_batch **out);
+
+/* dpd_batch_apply -- one persistent launch (plus one coefficient-precombine
+ * launch) on `stream`.  Allocates nothing, never synchronizes the host and
+ * may be captured in a hipGraph; the work counter resets itself at the end of
+ * each launch.  Calls that overlap in time on one batch race. */
+dpd_status dpd_batch_apply(dpd_batch *batch, void *stream);
+
+/* dpd_batch_apply_each -- reference schedule: one launch per stream with the
+ * same kernels as dpd_apply (for comparison against the persistent form). */
+dpd_status dpd_batch_apply_each(dpd_batch *batch, void *stream);
+
+/* dpd_batch_info -- number of tiles and persistent blocks of the batch. */
+dpd_status dpd_batch_info(const dpd_batch *batch, int64_t *n_tiles, int32_t *n_blocks);
+
+/* dpd_batch_destroy -- waits for the device, then frees the batch. */
+dpd_status dpd_batch_destroy(dpd_batch *batch);
+
+/* ------------------------------------------------------------------- misc -- */
+const char *dpd_status_string(dpd_status status);
+int dpd_last_hip_error(void);
+const char *dpd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPD_H */

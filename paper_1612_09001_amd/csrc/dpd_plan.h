@@ -1,0 +1,33 @@
+// Definition of the opaque plan / batch objects and host helpers shared by
+// the host translation units of libdpd.
+#pragma once
+
+#include <vector>
+
+#include "dpd.h"
+#include "dpd_internal.h"
+
+struct dpd_plan {
+    int device = 0;
+    dpd::CoefMap map;
+    int32_t K = 0;
+    dpd_tune tune;
+    std::vector<float> raw;      // host copy of the 2K coefficient floats
+    float *d_table = nullptr;    // precombined table (device)
+    void *d_ws = nullptr;        // reserved
+};
+
+namespace dpd {
+
+dpd_status hip_fail(hipError_t e);
+dpd_status make_map(const int32_t *mo, int32_t nm, const int32_t *co, int32_t nc, int32_t L,
+                    CoefMap &map);
+hipError_t launch_prep(const CoefMap &map, const void *raw, float *M, hipStream_t stream);
+dpd_status run_forward(const CoefMap &map, const dpd_tune &tune, const float *M, hipStream_t stream,
+                       const void *in, void *out, int64_t rows, int64_t n, int64_t ld,
+                       const void *hist);
+dpd_status check_io(const void *in, const void *out, int64_t rows, int64_t n, int64_t ld);
+dpd_tune default_tune();
+bool valid_tune(const dpd_tune &t);
+
+}  // namespace dpd

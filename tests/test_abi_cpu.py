@@ -1,0 +1,74 @@
+"""The C-ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before touching a device (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1612_09001_amd import dpd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dpd.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dpd_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(dpd.LIB_PATH):
+        pytest.skip("libdpd.so not built")
+    return dpd.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(dpd.EXPORTED) == declared
+
+
+def test_version_and_status_strings(lib):
+    assert "gfx950" in dpd.dpd_version()
+    for st in range(5):
+        assert dpd.dpd_status_string(st).startswith("DPD_")
+
+
+def _create(mo, co, L):
+    K = (len(mo) + len(co)) * L + 1
+    return dpd.dpd_create(mo, co, L, np.zeros(K, np.complex64))
+
+
+@pytest.mark.parametrize("mo,co,L,status", [
+    ([2], [], 3, dpd.DPD_EINVAL),          # even order
+    ([3, 1], [], 3, dpd.DPD_EINVAL),       # not ascending
+    ([1, 1], [], 3, dpd.DPD_EINVAL),       # duplicate
+    ([], [1], 3, dpd.DPD_EINVAL),          # no main branch
+    ([1], [], 0, dpd.DPD_EINVAL),          # L = 0
+    ([1], [], 17, dpd.DPD_EUNSUPPORTED),   # L > 16
+    ([1, 17], [], 2, dpd.DPD_EUNSUPPORTED),  # order > 15
+    ([-1], [], 2, dpd.DPD_EINVAL),
+])
+def test_create_rejects(lib, mo, co, L, status):
+    with pytest.raises(dpd.DPDError) as e:
+        _create(mo, co, L)
+    assert e.value.status == status
+
+
+def test_null_arguments(lib):
+    h = ctypes.c_void_p()
+    one = (ctypes.c_int32 * 1)(1)
+    assert lib.dpd_create(one, 1, None, 0, 2, None, ctypes.byref(h)) == dpd.DPD_EINVAL
+    c = (ctypes.c_float * 6)()
+    assert lib.dpd_create(one, 1, None, 0, 2, c, None) == dpd.DPD_EINVAL
+    assert lib.dpd_apply(None, None, None, None, 10) == dpd.DPD_EINVAL
+    assert lib.dpd_destroy(None) == dpd.DPD_OK
+    assert lib.dpd_num_coeffs(None, None) == dpd.DPD_EINVAL
+    assert lib.dpd_batch_create(None, 0, None, ctypes.byref(h)) == dpd.DPD_EINVAL
+    assert lib.dpd_batch_destroy(None) == dpd.DPD_OK
