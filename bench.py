@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
-    ap.add_argument("--tune", default="", help="S,LDS override, e.g. 4,1")
+    ap.add_argument("--tune", default="", help="S,LDS[,GRID_MULT] override, e.g. 2,1,8")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
@@ -107,8 +107,9 @@ def main():
     h = signals.aph_coeffs(mo, co, L, config_id=2)
     plan = dpd.Plan(mo, co, L, h)
     if args.tune:
-        s, lds = (int(v) for v in args.tune.split(","))
-        plan.set_tune(samples_per_thread=s, stage_lds=lds)
+        vals = [int(v) for v in args.tune.split(",")]
+        plan.set_tune(samples_per_thread=vals[0], stage_lds=vals[1],
+                      grid_mult=vals[2] if len(vals) > 2 else 8)
     tune = plan.get_tune()
 
     nbuf = max(2, ROTATE_BYTES // (2 * 8 * n))

@@ -179,6 +179,22 @@ __global__ void hist_update_kernel(const float2 *__restrict__ in, int64_t n, flo
 
 // --------------------------------------------------------------- tables ---
 
+// Compute units of the current device (cached per device id).
+int num_cus()
+{
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cache[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        cache[dev] = cus;
+    }
+    return cache[dev];
+}
+
 static FwdTable g_fwd;
 static std::once_flag g_fwd_once;
 
@@ -194,7 +210,8 @@ const FwdTable &fwd_table()
         register_fwd_ni6(g_fwd);
         register_fwd_ni7(g_fwd);
         register_fwd_ni8(g_fwd);
-        for (int v = 0; v < kNumFwdVariants; ++v) g_fwd.tile[v] = kBlock * (2 << (v / 2));
+        for (int v = 0; v < kNumFwdVariants; ++v)
+            g_fwd.tile[v] = (v & 1 ? 64 : kBlock) * (2 << (v / 2));
     });
     return g_fwd;
 }
@@ -215,10 +232,10 @@ bool valid_tune(const dpd_tune &t)
 dpd_tune default_tune()
 {
     dpd_tune t;
-    t.samples_per_thread = 4;
+    t.samples_per_thread = 8;
     t.stage_lds = 1;
     t.block = kBlock;
-    t.grid_mult = 8;
+    t.grid_mult = 16;   // capped at the resident-block limit of the kernel
     return t;
 }
 
@@ -254,7 +271,7 @@ dpd_status run_forward(const CoefMap &map, const dpd_tune &tune, const float *M,
         const int64_t T = t.tile[v];
         p.tiles_per_row = (n + T - 1) / T;
         p.total_tiles = p.tiles_per_row * rows;
-        hipError_t e = t.fn[map.NI - 1][map.L - 1][v](p, stream);
+        hipError_t e = t.fn[map.NI - 1][map.L - 1][v](p, stream, tune.grid_mult);
         return e == hipSuccess ? DPD_OK : hip_fail(e);
     }
     p.tiles_per_row = 0;

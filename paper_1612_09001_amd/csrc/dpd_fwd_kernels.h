@@ -120,23 +120,25 @@ __device__ __forceinline__ void store_outputs(float2 *__restrict__ z, int64_t m0
     }
 }
 
-// Tile = kBlock*S samples.  STAGE_LDS: the block loads its tile with coalesced
-// 16-byte loads into LDS (plus an even-padded halo of L-1 samples), then every
-// thread reads its S+L-1 window from LDS.  Otherwise each thread loads its own
-// window with 16-byte loads; the halo part re-reads its neighbour's samples,
-// which the vector L1 / L2 serve.
-template <int NI, int L, int S, bool STAGE_LDS>
-__global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams p)
+// One-shot kernel (stage_lds = 0): each block computes one tile of kBlock*S
+// outputs; every thread loads its own S+L-1 window with 16-byte loads (the
+// halo part re-reads its neighbour's samples, which the vector L1 / L2 serve).
+template <int NI, int L, int S>
+__global__ void __launch_bounds__(kBlock) fwd_tile_kernel(FwdParams p)
 {
     static_assert(S % 2 == 0, "S must be even (16-byte stores)");
     constexpr int T = kBlock * S;
     constexpr int HP = (L - 1 + 1) & ~1;   // halo rounded up to an even count
     constexpr int W = S + L - 1;
+    constexpr int WL = HP + S;              // loaded samples (even)
     __shared__ float ctop[4 * L];
-    __shared__ __align__(16) float2 xs[STAGE_LDS ? HP + T : 2];
 
     const int tid = threadIdx.x;
     if (tid < 4 * L) ctop[tid] = p.M[(tid >> 2) * 4 * NI + 4 * (NI - 1) + (tid & 3)];
+    __syncthreads();
+    float top[4 * L];
+#pragma unroll
+    for (int e = 0; e < 4 * L; ++e) top[e] = ctop[e];
 
     for (int64_t step = xcd_remap(blockIdx.x, gridDim.x); step < p.total_tiles; step += gridDim.x) {
         const int64_t row = step / p.tiles_per_row;
@@ -147,69 +149,293 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(FwdParams p)
         const bool full = t0 + T <= p.n;
         const int64_t m0 = t0 + (int64_t)tid * S;   // first output of this thread
 
-        float2 win[W];
-        if constexpr (STAGE_LDS) {
-            if (full) {
-                const float4 *x4 = reinterpret_cast<const float4 *>(x + t0);
-                float4 v[S / 2];
+        float2 raw[WL];
+        const int64_t lo = m0 - HP;
+        if (full && lo >= 0) {
+            const float4 *x4 = reinterpret_cast<const float4 *>(x + lo);
 #pragma unroll
-                for (int i = 0; i < S / 2; ++i) v[i] = x4[tid + i * kBlock];
-#pragma unroll
-                for (int i = 0; i < S / 2; ++i)
-                    reinterpret_cast<float4 *>(xs + HP)[tid + i * kBlock] = v[i];
-            } else {
-#pragma unroll
-                for (int i = 0; i < S; ++i) {
-                    const int q = tid + i * kBlock;
-                    xs[HP + q] = (t0 + q < p.n) ? x[t0 + q] : make_float2(0.f, 0.f);
-                }
+            for (int i = 0; i < WL / 2; ++i) {
+                float4 v = x4[i];
+                raw[2 * i] = make_float2(v.x, v.y);
+                raw[2 * i + 1] = make_float2(v.z, v.w);
             }
-            if (tid < HP) xs[tid] = sample_or_hist<L>(x, t0 - HP + tid, p.n, hist);
-            __syncthreads();
-            const int base = HP + tid * S - (L - 1);
-#pragma unroll
-            for (int w = 0; w < W; ++w) win[w] = xs[base + w];
         } else {
-            __syncthreads();   // ctop
-            constexpr int WL = HP + S;                  // loaded samples (even)
-            float2 raw[WL];
-            const int64_t lo = m0 - HP;
-            if (full && lo >= 0) {
-                const float4 *x4 = reinterpret_cast<const float4 *>(x + lo);
 #pragma unroll
-                for (int i = 0; i < WL / 2; ++i) {
-                    float4 v = x4[i];
-                    raw[2 * i] = make_float2(v.x, v.y);
-                    raw[2 * i + 1] = make_float2(v.z, v.w);
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < WL; ++i) raw[i] = sample_or_hist<L>(x, lo + i, p.n, hist);
-            }
-#pragma unroll
-            for (int w = 0; w < W; ++w) win[w] = raw[HP - (L - 1) + w];
+            for (int i = 0; i < WL; ++i) raw[i] = sample_or_hist<L>(x, lo + i, p.n, hist);
         }
-
-        float top[4 * L];
+        float2 win[W];
 #pragma unroll
-        for (int e = 0; e < 4 * L; ++e) top[e] = ctop[e];
+        for (int w = 0; w < W; ++w) win[w] = raw[HP - (L - 1) + w];
         float a[W], b[W], s[W];
         split_window<W>(win, a, b, s);
         float zr[S], zi[S];
         fir_outputs<NI, L, S>(a, b, s, top, as_const(p.M), zr, zi);
         if (m0 < p.n) store_outputs<S>(z, m0, p.n, full, zr, zi);
-        if constexpr (STAGE_LDS) __syncthreads();   // xs is reused by the next tile
     }
 }
 
-template <int NI, int L, int S, bool STAGE_LDS>
-hipError_t launch_fwd(const FwdParams &p, hipStream_t stream)
+// Compiler-only ordering point for LDS traffic between the lanes of one wave.
+// A wave's LDS instructions execute in program order, so no wait is needed;
+// this only stops the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void wave_lds_order()
 {
-    // Enough blocks to fill the chip several times over; larger inputs loop.
-    const int64_t cap = 1 << 20;
-    const int64_t grid = p.total_tiles < cap ? p.total_tiles : cap;
-    hipLaunchKernelGGL((fwd_kernel<NI, L, S, STAGE_LDS>), dim3((uint32_t)grid), dim3(kBlock), 0,
-                       stream, p);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Streaming kernel (stage_lds = 1).  Persistent grid of waves; at every step
+// the waves of the grid work on adjacent chunks of C = 64*S samples (wave g
+// takes chunks g, g + nw, g + 2 nw, ... of the flattened rows), so the whole
+// chip sweeps memory in order.  Per chunk:
+//   * the next D chunks are already in flight (register prefetch ring); every
+//     load instruction reads 1 KiB of contiguous memory (lane l, part i ->
+//     the 16 bytes at sample 2*(l + 64 i)), plus one broadcast 8-byte load per
+//     lane for the L-1 halo samples before the chunk (zeros at a row start,
+//     the caller's history before row 0);
+//   * samples and |x|^2 go to a wave-private LDS buffer laid out with one pad
+//     slot after every S samples (odd lane stride: conflict-free window reads);
+//     each lane reads its S+L-1 consecutive-sample window back, filters and
+//     stores 16-byte outputs.
+// The loop body has no divergent global accesses and the prefetch is
+// unconditional (past the end it re-reads the wave's last chunk, which the L2
+// still holds), so the compiler's counter waits stay exact.  The partial last
+// chunk of each row (when C does not divide n) is handled after the loop with
+// guarded accesses.  No block-wide barrier after the coefficient staging.
+template <int S>
+struct ChunkRegs {
+    float4 v[S / 2];
+    float2 h;   // raw halo sample for this lane's slot (selected at use)
+};
+
+// LDS slot of window sample d (relative to the chunk start, d >= -(L-1)).
+template <int L, int S>
+struct PadLayout {
+    static constexpr int HG = (L - 1 + S - 1) / S;          // pad groups before the chunk
+    static constexpr int OFF = HG * (S + 1);                // slot of sample 0
+    static constexpr int SLOTS = OFF + 64 * (S + 1);
+    __device__ static constexpr int slot(int d)
+    {
+        return OFF + d + (d >= 0 ? d / S : -((-d + S - 1) / S));
+    }
+};
+
+template <int NI, int L, int S, int D>
+__global__ void __launch_bounds__(kBlock) fwd_stream_kernel(FwdParams p)
+{
+    static_assert(S % 2 == 0, "S must be even (16-byte loads and stores)");
+    static_assert(D >= 1 && D <= 3, "prefetch depth 1..3");
+    constexpr int C = 64 * S;
+    constexpr int W = S + L - 1;
+    constexpr int NV = S / 2;
+    constexpr int WAVES = kBlock / 64;
+    using PL = PadLayout<L, S>;
+    constexpr int HS = L - 1;                        // halo samples
+    __shared__ float ctop[4 * L];
+    __shared__ __align__(16) float2 xs[WAVES][PL::SLOTS];
+    __shared__ __align__(16) float ss[WAVES][PL::SLOTS];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave
+    if (tid < 4 * L) ctop[tid] = p.M[(tid >> 2) * 4 * NI + 4 * (NI - 1) + (tid & 3)];
+    __syncthreads();
+    float top[4 * L];
+#pragma unroll
+    for (int e = 0; e < 4 * L; ++e) top[e] = ctop[e];
+    const cfloat *M = as_const(p.M);
+
+    float2 *X = xs[wv];
+    float *SX = ss[wv];
+    const int64_t rows = p.total_tiles / p.tiles_per_row;
+    const int64_t tpr = p.n / C;                 // full chunks per row
+    const int64_t total = rows * tpr;
+    const int64_t nw = (int64_t)gridDim.x * WAVES;
+    const int64_t gw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * WAVES + wv;
+    // halo sample this lane fetches: d = hl - HS in [-(L-1), -1]
+    const int hl = HS > 0 ? (lane < HS ? lane : HS - 1) : 0;
+    float2 hist_v = make_float2(0.f, 0.f);
+    if (HS > 0 && p.hist != nullptr) hist_v = p.hist[hl];
+
+    // raw sample for halo sample hl - HS of the chunk starting at t0 (clamped)
+    auto halo_raw = [&](int64_t row, int64_t t0) {
+        const int64_t m = t0 - HS + hl;
+        return p.in[row * p.ld + (m >= 0 ? m : 0)];
+    };
+
+    // samples -> LDS, windows -> registers, filter
+    auto filter_chunk = [&](const ChunkRegs<S> &buf, int64_t row, int64_t t0, float (&zr)[S],
+                            float (&zi)[S]) {
+        wave_lds_order();
+        if (HS > 0 && lane < HS) {
+            float2 h = buf.h;
+            if (t0 - HS + lane < 0) h = row == 0 ? hist_v : make_float2(0.f, 0.f);
+            const int q = PL::slot(lane - HS);
+            X[q] = h;
+            SX[q] = __builtin_fmaf(h.x, h.x, h.y * h.y);
+        }
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const float4 v = buf.v[i];
+            const int j = 2 * (lane + 64 * i);           // even, same pad group as j + 1
+            const int q = PL::OFF + j + j / S;
+            X[q] = make_float2(v.x, v.y);
+            X[q + 1] = make_float2(v.z, v.w);
+            SX[q] = __builtin_fmaf(v.x, v.x, v.y * v.y);
+            SX[q + 1] = __builtin_fmaf(v.z, v.z, v.w * v.w);
+        }
+        wave_lds_order();
+        float a[W], b[W], s[W];
+        const int lb = lane * (S + 1);
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int q = lb + PL::slot(w - (L - 1));
+            const float2 v = X[q];
+            a[w] = v.x;
+            b[w] = v.y;
+            s[w] = SX[q];
+        }
+        fir_outputs<NI, L, S>(a, b, s, top, M, zr, zi);
+    };
+
+    // Store the S outputs of every lane of a full chunk.  S = 2: each lane's
+    // 16 bytes are adjacent to its neighbour's, so the store instruction already
+    // writes 1 KiB contiguously.  S > 2: the outputs go back through the wave's
+    // LDS buffer and leave in the load order (lane l, part i -> samples
+    // 2*(l + 64 i)), so every store writes whole cache lines.
+    auto store_chunk = [&](float2 *zrow, int64_t t0, const float (&zr)[S], const float (&zi)[S]) {
+        if constexpr (S == 2) {
+            store_outputs<S>(zrow, t0 + lane * S, p.n, true, zr, zi);
+        } else {
+            wave_lds_order();
+            const int lb = lane * (S + 1) + PL::OFF;
+#pragma unroll
+            for (int i = 0; i < S; ++i) X[lb + i] = make_float2(zr[i], zi[i]);
+            wave_lds_order();
+            v4f *z4 = reinterpret_cast<v4f *>(zrow + t0);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int j = 2 * (lane + 64 * i);
+                const int q = PL::OFF + j + j / S;
+                const float2 u = X[q], w = X[q + 1];
+                const v4f v = {u.x, u.y, w.x, w.y};
+                __builtin_nontemporal_store(v, z4 + lane + 64 * i);
+            }
+        }
+    };
+
+    // ---- main loop over full chunks gw, gw + nw, ...
+    if (gw < total) {
+        // chunk c <-> (row, k); advancing by nw chunks without dividing
+        const int64_t dr = nw / tpr, dk = nw - (nw / tpr) * tpr;
+        struct Cur {
+            int64_t c, row, k;
+        };
+        const int64_t c_last = gw + ((total - 1 - gw) / nw) * nw;
+        auto advance = [&](Cur &u) {
+            if (u.c == c_last) return;       // clamp: keep re-reading the last chunk
+            u.c += nw;
+            u.row += dr;
+            u.k += dk;
+            if (u.k >= tpr) {
+                u.k -= tpr;
+                ++u.row;
+            }
+        };
+        auto load_full = [&](ChunkRegs<S> &buf, const Cur &u) {
+            const int64_t t0 = u.k * C;
+            const float4 *x4 = reinterpret_cast<const float4 *>(p.in + u.row * p.ld + t0);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) buf.v[i] = x4[lane + 64 * i];
+            buf.h = halo_raw(u.row, t0);
+        };
+        ChunkRegs<S> ring[D + 1];
+        Cur pos[D + 1];
+        Cur pf;                                       // prefetch cursor
+        pf.c = gw;
+        pf.row = gw / tpr;
+        pf.k = gw - pf.row * tpr;
+#pragma unroll
+        for (int u = 0; u < D; ++u) {
+            pos[u] = pf;
+            load_full(ring[u], pf);
+            advance(pf);
+        }
+        for (;;) {
+#pragma unroll
+            for (int u = 0; u <= D; ++u) {
+                const int nxt = (u + D) % (D + 1);
+                pos[nxt] = pf;
+                load_full(ring[nxt], pf);
+                advance(pf);
+                const Cur cur = pos[u];
+                float zr[S], zi[S];
+                filter_chunk(ring[u], cur.row, cur.k * C, zr, zi);
+                store_chunk(p.out + cur.row * p.ld, cur.k * C, zr, zi);
+                if (cur.c == c_last) goto done;
+            }
+        }
+    done:;
+    }
+
+    // ---- the partial last chunk of each row (when C does not divide n)
+    if (tpr * C < p.n) {
+        for (int64_t rw = gw; rw < rows; rw += nw) {
+            const int64_t t0 = tpr * C;
+            const float2 *x = p.in + rw * p.ld;
+            ChunkRegs<S> buf;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int64_t m = t0 + 2 * (lane + 64 * i);
+                const float2 u = m < p.n ? x[m] : make_float2(0.f, 0.f);
+                const float2 w = m + 1 < p.n ? x[m + 1] : make_float2(0.f, 0.f);
+                buf.v[i] = make_float4(u.x, u.y, w.x, w.y);
+            }
+            buf.h = halo_raw(rw, t0);
+            float zr[S], zi[S];
+            filter_chunk(buf, rw, t0, zr, zi);
+            const int64_t m0 = t0 + (int64_t)lane * S;
+            float2 *z = p.out + rw * p.ld;
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+                if (m0 + i < p.n) z[m0 + i] = make_float2(zr[i], zi[i]);
+        }
+    }
+}
+
+template <int S>
+struct PrefetchDepth {
+    static constexpr int value = S == 2 ? 3 : (S == 4 ? 2 : 1);
+};
+
+int num_cus();
+
+template <int NI, int L, int S, bool STREAM>
+hipError_t launch_fwd(const FwdParams &p, hipStream_t stream, int grid_mult)
+{
+    int64_t grid;
+    if constexpr (STREAM) {
+        // persistent: grid_mult blocks per CU, never more than one chunk per wave
+        // never more blocks than can be resident at once (a second round of a
+        // persistent grid would double the tail)
+        static const int occ = [] {
+            int o = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, fwd_stream_kernel<NI, L, S, PrefetchDepth<S>::value>, kBlock,
+                                                             0) != hipSuccess || o < 1)
+                o = 1;
+            return o;
+        }();
+        const int64_t want = (int64_t)num_cus() * (grid_mult < occ ? grid_mult : occ);
+        const int64_t need = (p.total_tiles + kBlock / 64 - 1) / (kBlock / 64);   // >= 1 wave per chunk
+        grid = need < want ? need : want;
+        hipLaunchKernelGGL((fwd_stream_kernel<NI, L, S, PrefetchDepth<S>::value>), dim3((uint32_t)grid),
+                           dim3(kBlock), 0,
+                           stream, p);
+    } else {
+        const int64_t cap = 1 << 20;
+        grid = p.total_tiles < cap ? p.total_tiles : cap;
+        hipLaunchKernelGGL((fwd_tile_kernel<NI, L, S>), dim3((uint32_t)grid), dim3(kBlock), 0,
+                           stream, p);
+    }
     return hipGetLastError();
 }
 

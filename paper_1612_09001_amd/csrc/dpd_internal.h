@@ -16,7 +16,9 @@ constexpr int kSpecL = 8;
 constexpr int kBlock = 256;
 
 // Launch variants of the specialised forward kernel:
-//   variant = s_index * 2 + stage_lds,   samples per thread = 2 << s_index.
+//   variant = s_index * 2 + stage_lds,   samples per thread = 2 << s_index;
+//   stage_lds = 0: one-shot tiles, windows loaded directly;
+//   stage_lds = 1: persistent streaming kernel, windows staged through LDS.
 constexpr int kNumSIdx = 3;                 // S in {2, 4, 8}
 constexpr int kNumFwdVariants = kNumSIdx * 2;
 
@@ -50,11 +52,11 @@ struct FwdParams {
     const float2 *hist;    // L-1 samples preceding row 0, or nullptr
 };
 
-typedef hipError_t (*FwdLaunch)(const FwdParams &, hipStream_t);
+typedef hipError_t (*FwdLaunch)(const FwdParams &, hipStream_t, int grid_mult);
 
 struct FwdTable {
     FwdLaunch fn[kSpecNI][kSpecL][kNumFwdVariants];
-    int tile[kNumFwdVariants];   // samples per block tile of each variant
+    int tile[kNumFwdVariants];   // samples per tile (one-shot) or per wave chunk (streaming)
 };
 
 // Registration hooks, one per power-level translation unit.
