@@ -31,6 +31,8 @@ FLAGS = [
 # (source, extra defines, object name)
 UNITS = [("dpd_api.hip", [], "dpd_api.o")]
 UNITS += [("dpd_fwd_inst.hip", ["-DDPD_NI=%d" % k], "dpd_fwd_ni%d.o" % k) for k in range(1, 9)]
+UNITS += [("dpd_bwd_inst.hip", ["-DDPD_NI=%d" % k], "dpd_bwd_ni%d.o" % k) for k in range(1, 9)]
+UNITS += [("dpd_bwd.hip", [], "dpd_bwd.o")]
 UNITS += [("dpd_stubs.hip", [], "dpd_stubs.o")]
 
 

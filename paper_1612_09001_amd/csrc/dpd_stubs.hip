@@ -1,7 +1,5 @@
 #include "dpd_plan.h"
 #define DPD_EXPORT extern "C" __attribute__((visibility("default")))
-DPD_EXPORT dpd_status dpd_backward_ws_size(const dpd_plan *, int64_t, int64_t, size_t *) { return DPD_EUNSUPPORTED; }
-DPD_EXPORT dpd_status dpd_backward(dpd_plan *, void *, const void *, const void *, const void *, void *, void *, int64_t, int64_t, int64_t, void *, size_t) { return DPD_EUNSUPPORTED; }
 DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *d, int32_t, const dpd_tune *, dpd_batch **o) { return (!d || !o) ? DPD_EINVAL : DPD_EUNSUPPORTED; }
 DPD_EXPORT dpd_status dpd_batch_apply(dpd_batch *, void *) { return DPD_EUNSUPPORTED; }
 DPD_EXPORT dpd_status dpd_batch_apply_each(dpd_batch *, void *) { return DPD_EUNSUPPORTED; }
