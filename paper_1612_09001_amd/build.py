@@ -33,7 +33,8 @@ UNITS = [("dpd_api.hip", [], "dpd_api.o")]
 UNITS += [("dpd_fwd_inst.hip", ["-DDPD_NI=%d" % k], "dpd_fwd_ni%d.o" % k) for k in range(1, 9)]
 UNITS += [("dpd_bwd_inst.hip", ["-DDPD_NI=%d" % k], "dpd_bwd_ni%d.o" % k) for k in range(1, 9)]
 UNITS += [("dpd_bwd.hip", [], "dpd_bwd.o")]
-UNITS += [("dpd_stubs.hip", [], "dpd_stubs.o")]
+UNITS += [("dpd_batch_inst.hip", ["-DDPD_BATCH_S=%d" % s], "dpd_batch_s%d.o" % s) for s in (2, 4, 8)]
+UNITS += [("dpd_batch.hip", [], "dpd_batch.o")]
 
 
 def _compile(unit):

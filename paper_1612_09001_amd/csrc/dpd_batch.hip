@@ -1,0 +1,295 @@
+// Host side of the batched multi-stream apply (dpd_batch_*).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "dpd.h"
+#include "dpd_batch_kernels.h"
+#include "dpd_plan.h"
+
+#define DPD_EXPORT extern "C" __attribute__((visibility("default")))
+
+struct dpd_batch {
+    int device = 0;
+    int32_t n_streams = 0;
+    std::vector<dpd_stream_desc> desc;
+    std::vector<dpd::CoefMap> maps;
+    std::vector<int32_t> tab;
+    std::vector<int32_t> fallback;       // streams run by separate launches
+    dpd::BatchStream *d_streams = nullptr;
+    dpd::BatchItem *d_items = nullptr;
+    dpd::BatchPrep *d_prep = nullptr;
+    float *d_tables = nullptr;
+    unsigned int *d_counter = nullptr;
+    int64_t n_items = 0;
+    int grid = 0;
+    int sidx = 2;
+    dpd_tune tune;
+};
+
+namespace dpd {
+
+int num_cus();
+
+// One block per stream: precombine its coefficients into the batch table.
+__global__ void __launch_bounds__(128) batch_prep_kernel(const BatchPrep *__restrict__ prep,
+                                                         float *__restrict__ tables)
+{
+    const BatchPrep bp = prep[blockIdx.x];
+    const int L = bp.map.L, NI = bp.map.NI, t = threadIdx.x;
+    float *M = tables + bp.tab;
+    if (t < L * NI) {
+        const int k = t / NI, j = t - k * NI;
+        float2 h = make_float2(0.f, 0.f), g = make_float2(0.f, 0.f);
+        if (bp.map.main_idx[j] >= 0) h = bp.raw[bp.map.main_idx[j] * L + k];
+        if (bp.map.conj_idx[j] >= 0) g = bp.raw[(bp.map.n_main + bp.map.conj_idx[j]) * L + k];
+        M[4 * t + 0] = h.x + g.x;
+        M[4 * t + 1] = g.y - h.y;
+        M[4 * t + 2] = h.y + g.y;
+        M[4 * t + 3] = h.x - g.x;
+    }
+    if (t == 0) {
+        const int K = (bp.map.n_main + bp.map.n_conj) * L + 1;
+        const float2 c = bp.raw[K - 1];
+        M[4 * L * NI] = c.x;
+        M[4 * L * NI + 1] = c.y;
+    }
+}
+
+static BatchTable g_batch;
+static std::once_flag g_batch_once;
+
+static const BatchTable &batch_table()
+{
+    std::call_once(g_batch_once, [] {
+        std::memset(&g_batch, 0, sizeof(g_batch));
+        register_batch_s2(g_batch);
+        register_batch_s4(g_batch);
+        register_batch_s8(g_batch);
+    });
+    return g_batch;
+}
+
+static int batch_occupancy(int sidx)
+{
+    static int cache[kNumSIdx] = {};
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache[sidx] == 0) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, batch_table().kern[sidx], kBlock, 0) !=
+                hipSuccess ||
+            v < 1)
+            v = 1;
+        cache[sidx] = v;
+    }
+    return cache[sidx];
+}
+
+static void free_batch(dpd_batch *b)
+{
+    if (b->d_streams) (void)hipFree(b->d_streams);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_prep) (void)hipFree(b->d_prep);
+    if (b->d_tables) (void)hipFree(b->d_tables);
+    if (b->d_counter) (void)hipFree(b->d_counter);
+    delete b;
+}
+
+template <class T>
+static hipError_t upload(T **dst, const std::vector<T> &v)
+{
+    const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+    hipError_t e = hipMalloc((void **)dst, bytes);
+    if (e != hipSuccess) return e;
+    if (!v.empty()) e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+static dpd_status batch_prep(dpd_batch *b, hipStream_t st)
+{
+    if (b->n_streams == 0) return DPD_OK;
+    hipLaunchKernelGGL(batch_prep_kernel, dim3((uint32_t)b->n_streams), dim3(128), 0, st, b->d_prep,
+                       b->d_tables);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DPD_OK : hip_fail(e);
+}
+
+static dpd_status run_stream(dpd_batch *b, int s, hipStream_t st)
+{
+    const dpd_stream_desc &d = b->desc[s];
+    if (d.n == 0) return DPD_OK;
+    return run_forward(b->maps[s], default_tune(), b->d_tables + b->tab[s], st, d.in, d.out, 1, d.n, d.n,
+                       nullptr);
+}
+
+}  // namespace dpd
+
+using namespace dpd;
+
+DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_streams, const dpd_tune *tune,
+                                       dpd_batch **out)
+{
+    if (out == nullptr || n_streams < 0 || (n_streams > 0 && desc == nullptr)) return DPD_EINVAL;
+    if (desc == nullptr) return DPD_EINVAL;
+    dpd_tune t = default_tune();
+    if (tune != nullptr) {
+        if (!valid_tune(*tune) || tune->stage_lds != 1) return DPD_EINVAL;
+        t = *tune;
+    }
+    dpd_batch *b = new (std::nothrow) dpd_batch();
+    if (b == nullptr) return DPD_ENOMEM;
+    b->tune = t;
+    b->sidx = t.samples_per_thread == 2 ? 0 : (t.samples_per_thread == 4 ? 1 : 2);
+    b->n_streams = n_streams;
+    b->desc.assign(desc, desc + n_streams);
+    std::vector<BatchStream> streams(n_streams);
+    std::vector<BatchPrep> prep(n_streams);
+    std::vector<BatchItem> items;
+    int64_t tab_total = 0;
+    for (int32_t s = 0; s < n_streams; ++s) {
+        const dpd_stream_desc &d = desc[s];
+        int32_t mo[kMaxNI], co[kMaxNI], nm = 0, nc = 0;
+        if ((d.main_mask >> kMaxNI) != 0 || (d.conj_mask >> kMaxNI) != 0) {
+            free_batch(b);
+            return DPD_EUNSUPPORTED;
+        }
+        for (int j = 0; j < kMaxNI; ++j) {
+            if (d.main_mask & (1u << j)) mo[nm++] = 2 * j + 1;
+            if (d.conj_mask & (1u << j)) co[nc++] = 2 * j + 1;
+        }
+        CoefMap map;
+        dpd_status st = make_map(mo, nm, co, nc, d.L, map);
+        if (st == DPD_OK && (d.n < 0 || d.coeffs_dev == nullptr || (uintptr_t)d.coeffs_dev % 8 != 0))
+            st = DPD_EINVAL;
+        if (st == DPD_OK) st = check_io(d.in, d.out, 1, d.n, d.n);
+        if (st != DPD_OK) {
+            free_batch(b);
+            return st;
+        }
+        b->maps.push_back(map);
+        b->tab.push_back((int32_t)tab_total);
+        prep[s].raw = (const float2 *)d.coeffs_dev;
+        prep[s].map = map;
+        prep[s].tab = (int32_t)tab_total;
+        tab_total += (table_floats(map.L, map.NI) + 3) & ~3;
+        const bool aligned = (uintptr_t)d.in % 16 == 0 && (uintptr_t)d.out % 16 == 0;
+        const bool in_kernel = aligned && map.NI <= kBatchMaxNI && map.L <= kBatchMaxL;
+        streams[s].in = (const float2 *)d.in;
+        streams[s].out = (float2 *)d.out;
+        streams[s].n = d.n;
+        streams[s].tab = prep[s].tab;
+        streams[s].cls = in_kernel ? (map.NI - 1) * kBatchMaxL + (map.L - 1) : -1;
+        if (!in_kernel) {
+            b->fallback.push_back(s);
+            continue;
+        }
+        for (int64_t t0 = 0; t0 < d.n; t0 += kBatchItem) {
+            BatchItem it;
+            it.stream = s;
+            it.pad_ = 0;
+            it.t0 = t0;
+            items.push_back(it);
+        }
+    }
+    // no stream may write where another reads or writes
+    for (int32_t s = 0; s < n_streams; ++s) {
+        const size_t bs = (size_t)desc[s].n * 8;
+        for (int32_t r = 0; r < n_streams && bs > 0; ++r) {
+            if (r == s || desc[r].n == 0) continue;
+            const size_t br = (size_t)desc[r].n * 8;
+            const uintptr_t o = (uintptr_t)desc[s].out;
+            const uintptr_t i = (uintptr_t)desc[r].in, w = (uintptr_t)desc[r].out;
+            if ((o < i + br && i < o + bs) || (o < w + br && w < o + bs)) {
+                free_batch(b);
+                return DPD_EINVAL;
+            }
+        }
+    }
+    if ((int64_t)items.size() >= (int64_t)1 << 30 || tab_total >= (int64_t)1 << 30) {
+        free_batch(b);
+        return DPD_EUNSUPPORTED;
+    }
+    // most expensive items first: per-sample cost ~ NI * L, full items before
+    // the partial last item of a stream; ties keep stream order
+    auto cost = [&](const BatchItem &it) {
+        const CoefMap &m = b->maps[it.stream];
+        const int64_t len = std::min<int64_t>(kBatchItem, desc[it.stream].n - it.t0);
+        return (int64_t)m.NI * m.L * len;
+    };
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const BatchItem &a, const BatchItem &c) { return cost(a) > cost(c); });
+    b->n_items = (int64_t)items.size();
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) e = upload(&b->d_streams, streams);
+    if (e == hipSuccess) e = upload(&b->d_items, items);
+    if (e == hipSuccess) e = upload(&b->d_prep, prep);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_tables, std::max<int64_t>(tab_total, 4) * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, 2 * sizeof(unsigned int));
+    if (e == hipSuccess) e = hipMemset(b->d_counter, 0, 2 * sizeof(unsigned int));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_batch(b);
+        return e == hipErrorOutOfMemory ? DPD_ENOMEM : hip_fail(e);
+    }
+    const int64_t cap = (int64_t)num_cus() * std::min(t.grid_mult, batch_occupancy(b->sidx));
+    b->grid = (int)std::max<int64_t>(1, std::min<int64_t>(cap, b->n_items));
+    *out = b;
+    return DPD_OK;
+}
+
+DPD_EXPORT dpd_status dpd_batch_apply(dpd_batch *b, void *stream)
+{
+    if (b == nullptr) return DPD_EINVAL;
+    const hipStream_t st = (hipStream_t)stream;
+    dpd_status s = batch_prep(b, st);
+    if (s != DPD_OK) return s;
+    if (b->n_items > 0) {
+        BatchParams bp;
+        bp.streams = b->d_streams;
+        bp.items = b->d_items;
+        bp.n_items = b->n_items;
+        bp.tables = b->d_tables;
+        bp.counter = b->d_counter;
+        hipError_t e = batch_table().fn[b->sidx](bp, st, b->grid);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    for (int32_t idx : b->fallback) {
+        s = run_stream(b, idx, st);
+        if (s != DPD_OK) return s;
+    }
+    return DPD_OK;
+}
+
+DPD_EXPORT dpd_status dpd_batch_apply_each(dpd_batch *b, void *stream)
+{
+    if (b == nullptr) return DPD_EINVAL;
+    const hipStream_t st = (hipStream_t)stream;
+    dpd_status s = batch_prep(b, st);
+    if (s != DPD_OK) return s;
+    for (int32_t i = 0; i < b->n_streams; ++i) {
+        s = run_stream(b, i, st);
+        if (s != DPD_OK) return s;
+    }
+    return DPD_OK;
+}
+
+DPD_EXPORT dpd_status dpd_batch_info(const dpd_batch *b, int64_t *n_tiles, int32_t *n_blocks)
+{
+    if (b == nullptr || n_tiles == nullptr || n_blocks == nullptr) return DPD_EINVAL;
+    *n_tiles = b->n_items;
+    *n_blocks = b->grid;
+    return DPD_OK;
+}
+
+DPD_EXPORT dpd_status dpd_batch_destroy(dpd_batch *b)
+{
+    if (b == nullptr) return DPD_OK;
+    hipError_t e = hipDeviceSynchronize();
+    free_batch(b);
+    return e == hipSuccess ? DPD_OK : hip_fail(e);
+}

@@ -1,0 +1,132 @@
+"""Batched persistent multi-stream apply against the oracle and against the
+per-stream launches; hipGraph replay; self-resetting work counter."""
+import numpy as np
+import pytest
+
+from metrics import assert_parity
+from paper_1612_09001_amd import signals
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def mods(torch):
+    from paper_1612_09001_amd import batch, dpd
+
+    dpd.lib()
+    return dpd, batch
+
+
+SMALL_SPECS = [  # (n, P_max, L) -- ragged lengths, every class shape, fallbacks
+    (0, 5, 3), (1, 5, 2), (7, 7, 8), (4095, 9, 8), (4096, 5, 1), (4097, 7, 4), (20000, 3, 6),
+    (12345, 1, 5), (70001, 9, 2), (3, 11, 3), (5000, 5, 11), (65536, 7, 4), (1023, 9, 5),
+]
+
+
+def _check_streams(wl, z, orc, count=None):
+    rng = np.random.default_rng(1)
+    for s, (n, pmax, L) in enumerate(wl.specs):
+        if n == 0:
+            continue
+        orders = signals.odd_orders(pmax)
+        x = wl.stream_input(s)
+        got = z[wl.offsets[s]:wl.offsets[s] + n]
+        h = wl.coeffs_host[s]
+        if count is None or n <= count:
+            ref = orc.forward(x, orders, orders, L, h)
+            assert_parity(got, ref, "stream %d" % s)
+        else:
+            edges = (np.arange(1, n // 4096 + 1) * 4096)[:, None] + np.arange(-9, 9)[None, :]
+            idx = np.unique(np.concatenate([np.arange(0, 20), np.arange(n - 20, n), edges.reshape(-1)]))
+            idx = idx[(idx >= 0) & (idx < n)]
+            idx = np.unique(np.concatenate([idx, rng.integers(0, n, count)]))
+            assert_parity(got[idx], orc.forward_at(x, orders, orders, L, h, idx), "stream %d" % s)
+
+
+@pytest.mark.parametrize("S", [2, 4, 8])
+def test_small_batch_matches_oracle_and_each(torch, mods, orc, S):
+    dpd, batch = mods
+    wl = batch.BatchWorkload(SMALL_SPECS, config_id=70)
+    b = batch.Batch(wl.streams(), tune={"samples_per_thread": S, "grid_mult": 4})
+    wl.z.fill_(complex(7.0, -7.0))
+    b.apply()
+    z1 = wl.z.cpu().numpy()
+    _check_streams(wl, z1, orc)
+    wl.z.fill_(complex(7.0, -7.0))
+    b.apply_each()
+    z2 = wl.z.cpu().numpy()
+    assert np.array_equal(z1, z2), "persistent batch differs from per-stream launches"
+    # padding slots between streams are never written
+    for s, (n, _, _) in enumerate(wl.specs):
+        if n % 2:
+            assert z1[wl.offsets[s] + n] == np.complex64(complex(7.0, -7.0))
+    b.close()
+
+
+def _written(wl, z):
+    """Concatenation of the stream regions (the padding between is never written)."""
+    return np.concatenate([z[o:o + n] for o, (n, _, _) in zip(wl.offsets, wl.specs)])
+
+
+def test_counter_resets_and_graph_replay(torch, mods):
+    dpd, batch = mods
+    wl = batch.BatchWorkload(SMALL_SPECS, config_id=71)
+    b = batch.Batch(wl.streams())
+    b.apply()
+    ref = _written(wl, wl.z.cpu().numpy())
+    for _ in range(3):
+        wl.z.fill_(0)
+        b.apply()
+        assert np.array_equal(_written(wl, wl.z.cpu().numpy()), ref)
+    g = torch.cuda.CUDAGraph()
+    wl.z.fill_(0)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        b.apply()
+    for r in range(4):
+        wl.z.fill_(complex(r, -r))          # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(_written(wl, wl.z.cpu().numpy()), ref), "replay %d" % r
+    b.apply()
+    assert np.array_equal(_written(wl, wl.z.cpu().numpy()), ref)
+
+
+def test_invalid_descriptors(torch, mods):
+    dpd, batch = mods
+    x = torch.zeros(100, dtype=torch.complex64, device="cuda")
+    c = torch.zeros(20, dtype=torch.complex64, device="cuda")
+    bad = [
+        dict(main_orders=[1, 17], conj_orders=[], L=2),   # order > 15 (mask bit 8)
+        dict(main_orders=[], conj_orders=[1], L=2),       # no main branch
+        dict(main_orders=[1], conj_orders=[], L=0),
+        dict(main_orders=[1], conj_orders=[], L=17),
+    ]
+    for kw in bad:
+        with pytest.raises(dpd.DPDError):
+            batch.Batch([dict(kw, **{"in": x[:50], "out": x[50:], "n": 50, "coeffs": c})])
+    with pytest.raises(dpd.DPDError):   # stream 1 writes over stream 0's input
+        batch.Batch([dict(main_orders=[1], conj_orders=[], L=2, **{"in": x[:50], "out": x[50:], "n": 50, "coeffs": c}),
+                     dict(main_orders=[1], conj_orders=[], L=2, **{"in": x[60:70], "out": x[:10], "n": 10, "coeffs": c})])
+
+
+def test_config4_full_sampled(torch, mods, orc):
+    """256 streams, lengths U[2^14, 2^20], P_max in {5,7,9}, L in {2..8}."""
+    dpd, batch = mods
+    wl = batch.BatchWorkload(signals.batch_specs(), config_id=4)
+    b = batch.Batch(wl.streams())
+    ntiles, nblocks = b.info()
+    assert ntiles == sum((n + 4095) // 4096 for n, _, _ in wl.specs)
+    b.apply()
+    z = wl.z.cpu().numpy()
+    _check_streams(wl, z, orc, count=2000)
