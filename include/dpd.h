@@ -189,6 +189,29 @@ dpd_status dpd_batch_info(const dpd_batch *batch, int64_t *n_tiles, int32_t *n_b
 /* dpd_batch_destroy -- waits for the device, then frees the batch. */
 dpd_status dpd_batch_destroy(dpd_batch *batch);
 
+/* --------------------------------------------------------------- training --
+ * Helpers that let a coefficient-learning step (predistorter -> fixed PA
+ * model -> loss -> backward -> Adam) run entirely in libdpd kernels.  Not in
+ * the paper, whose training is offline least squares (section 2.2).
+ *
+ * dpd_loss_grad -- E = (1/n) sum_t |scale*y_t - x_t|^2 over n complex64
+ * samples (y: PA output, x: the original input, scale: 1/PA gain), written as
+ * one float to *loss_dev (device; may be NULL), and dE/dRe y + j dE/dIm y =
+ * (2 scale / n)(scale*y - x) written to grad_y (device, n complex64; may be
+ * NULL).  Deterministic (fixed-order FP64 sum of per-block partials).  ws: device
+ * workspace of dpd_loss_ws_size() bytes, owned by the caller. */
+dpd_status dpd_loss_ws_size(int64_t n, size_t *bytes);
+dpd_status dpd_loss_grad(void *stream, const void *y, const void *x, int64_t n, float scale,
+                         float *loss_dev, void *grad_y, void *ws, size_t ws_bytes);
+
+/* dpd_adam_step -- one Adam update (Kingma & Ba) of `count` real parameters
+ * in device memory (a complex coefficient vector is 2K interleaved floats):
+ *   m = b1 m + (1-b1) g,  v = b2 v + (1-b2) g^2,
+ *   p -= (lr / (1 - b1^step)) m / (sqrt(v / (1 - b2^step)) + eps).
+ * step counts from 1.  m and v are caller-owned state (zero before step 1). */
+dpd_status dpd_adam_step(void *stream, float *params, const float *grads, float *m, float *v,
+                         int64_t count, int32_t step, float lr, float beta1, float beta2, float eps);
+
 /* ------------------------------------------------------------------- misc -- */
 const char *dpd_status_string(dpd_status status);
 int dpd_last_hip_error(void);

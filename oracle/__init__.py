@@ -8,3 +8,4 @@ from .oracle import (  # noqa: F401
     Oracle, forward, forward_at, backward, ls_normal, threads, build, lib_path,
 )
 from . import brute  # noqa: F401
+from . import pa  # noqa: F401,E402

@@ -69,6 +69,10 @@ _SIGS = {
     "dpd_batch_apply_each": [_vp, _vp],
     "dpd_batch_info": [_vp, ctypes.POINTER(_i64), _i32p],
     "dpd_batch_destroy": [_vp],
+    "dpd_loss_ws_size": [_i64, ctypes.POINTER(ctypes.c_size_t)],
+    "dpd_loss_grad": [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _vp, ctypes.c_size_t],
+    "dpd_adam_step": [_vp, _vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float,
+                      ctypes.c_float, ctypes.c_float],
 }
 
 # Symbols the header declares (checked by the CPU test-suite).
@@ -229,6 +233,23 @@ def dpd_batch_info(batch):
 
 def dpd_batch_destroy(batch):
     _check(lib().dpd_batch_destroy(batch), "dpd_batch_destroy")
+
+
+def dpd_loss_ws_size(n) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().dpd_loss_ws_size(int(n), ctypes.byref(b)), "dpd_loss_ws_size")
+    return b.value
+
+
+def dpd_loss_grad(stream, y_ptr, x_ptr, n, scale, loss_ptr, gy_ptr, ws_ptr, ws_bytes):
+    _check(lib().dpd_loss_grad(stream, y_ptr, x_ptr, int(n), float(scale), loss_ptr, gy_ptr, ws_ptr,
+                               int(ws_bytes)), "dpd_loss_grad")
+
+
+def dpd_adam_step(stream, p_ptr, g_ptr, m_ptr, v_ptr, count, step, lr, beta1=0.9, beta2=0.999,
+                  eps=1e-8):
+    _check(lib().dpd_adam_step(stream, p_ptr, g_ptr, m_ptr, v_ptr, int(count), int(step), float(lr),
+                               float(beta1), float(beta2), float(eps)), "dpd_adam_step")
 
 
 # ------------------------------------------------------- tensor wrappers ---

@@ -1,0 +1,111 @@
+"""Learning predistorter coefficients through the fixed synthetic PA.
+
+``FusedTrainer.step()`` runs one full-batch gradient step entirely in libdpd
+kernels, on buffers allocated once:
+
+  z = DPD(x)                 forward, coefficients read from the device
+  u = IQ(z), y = PA(u)       the synthetic transmitter (pa.py)
+  E, dE/dy                   loss E = mean |y/G - x|^2 and its gradient
+  dE/du, dE/dz               adjoint of PA and IQ (input gradients only)
+  dE/dcoeffs                 adjoint of the predistorter (coefficients only)
+  Adam                       update of the K complex coefficients
+
+``AutogradTrainer`` is the same step through ``torch.autograd`` with the
+predistorter and both PA stages as ``DPDFunction`` nodes (hand-written
+adjoint kernels), a PyTorch loss and ``torch.optim.Adam``.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import dpd as _dpd
+from .autograd import DPDFunction
+from .pa import SyntheticPA, iq_coeffs, pa_coeffs
+
+
+class FusedTrainer:
+    def __init__(self, x, main_orders, conj_orders, L, coeffs0, lr=1e-3, betas=(0.9, 0.999),
+                 eps=1e-8):
+        if x.dim() != 2 or not x.is_contiguous():
+            raise ValueError("x must be a contiguous (rows, n) complex64 GPU tensor")
+        self.x = x
+        self.rows, self.n = x.shape
+        self.plan = _dpd.Plan(main_orders, conj_orders, L, np.asarray(coeffs0))
+        self.K = self.plan.K
+        dev = x.device
+        self.coeffs = torch.as_tensor(np.asarray(coeffs0, dtype=np.complex64)).to(dev).contiguous()
+        self.pa = SyntheticPA()
+        self.z = torch.empty_like(x)
+        self.u = torch.empty_like(x)
+        self.y = torch.empty_like(x)
+        self.gy = torch.empty_like(x)
+        self.gu = torch.empty_like(x)
+        self.gz = torch.empty_like(x)
+        self.gc = torch.empty(self.K, dtype=torch.complex64, device=dev)
+        self.m = torch.zeros(2 * self.K, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(2 * self.K, dtype=torch.float32, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.t = 0
+        ws = max(_dpd.dpd_backward_ws_size(p.handle, self.rows, self.n)
+                 for p in (self.plan, self.pa.iq, self.pa.pa))
+        self.ws_bytes = max(ws, _dpd.dpd_loss_ws_size(self.rows * self.n))
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+
+    def step(self):
+        """One gradient step; returns the loss of the coefficients before it
+        (a device tensor, no host synchronization)."""
+        st = _dpd.current_stream()
+        R, N, ld = self.rows, self.n, self.n
+        P = lambda t: t.data_ptr()
+        _dpd.dpd_apply_coeffs(self.plan.handle, st, P(self.coeffs), P(self.x), P(self.z), R, N, ld)
+        _dpd.dpd_apply_rows(self.pa.iq.handle, st, P(self.z), P(self.u), R, N, ld)
+        _dpd.dpd_apply_rows(self.pa.pa.handle, st, P(self.u), P(self.y), R, N, ld)
+        _dpd.dpd_loss_grad(st, P(self.y), P(self.x), R * N, 1.0 / self.pa.gain, P(self.loss),
+                           P(self.gy), P(self.ws), self.ws_bytes)
+        _dpd.dpd_backward(self.pa.pa.handle, st, 0, P(self.u), P(self.gy), P(self.gu), 0, R, N, ld,
+                          P(self.ws), self.ws_bytes)
+        _dpd.dpd_backward(self.pa.iq.handle, st, 0, P(self.z), P(self.gu), P(self.gz), 0, R, N, ld,
+                          P(self.ws), self.ws_bytes)
+        _dpd.dpd_backward(self.plan.handle, st, P(self.coeffs), P(self.x), P(self.gz), 0, P(self.gc),
+                          R, N, ld, P(self.ws), self.ws_bytes)
+        self.t += 1
+        _dpd.dpd_adam_step(st, P(self.coeffs), P(self.gc), P(self.m), P(self.v), 2 * self.K, self.t,
+                           self.lr, self.betas[0], self.betas[1], self.eps)
+        return self.loss
+
+    def state_dict(self):
+        return {"coeffs": self.coeffs.clone(), "m": self.m.clone(), "v": self.v.clone(), "t": self.t}
+
+    def load_state_dict(self, d):
+        self.coeffs.copy_(d["coeffs"])
+        self.m.copy_(d["m"])
+        self.v.copy_(d["v"])
+        self.t = int(d["t"])
+
+
+class AutogradTrainer:
+    def __init__(self, x, main_orders, conj_orders, L, coeffs0, lr=1e-3):
+        self.x = x
+        self.plan = _dpd.Plan(main_orders, conj_orders, L, np.asarray(coeffs0))
+        self.pa = SyntheticPA()
+        dev = x.device
+        self.coeffs = torch.nn.Parameter(
+            torch.as_tensor(np.asarray(coeffs0, dtype=np.complex64)).to(dev).clone())
+        self.iq_c = torch.as_tensor(iq_coeffs()).to(dev)
+        self.pa_c = torch.as_tensor(pa_coeffs()).to(dev)
+        self.opt = torch.optim.Adam([self.coeffs], lr=lr)
+
+    def loss_fn(self):
+        z = DPDFunction.apply(self.x, self.coeffs, self.plan)
+        u = DPDFunction.apply(z, self.iq_c, self.pa.iq)
+        y = DPDFunction.apply(u, self.pa_c, self.pa.pa)
+        return (torch.abs(y / self.pa.gain - self.x) ** 2).mean()
+
+    def step(self):
+        self.opt.zero_grad(set_to_none=True)
+        loss = self.loss_fn()
+        loss.backward()
+        self.opt.step()
+        return loss.detach()

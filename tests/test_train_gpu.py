@@ -1,0 +1,83 @@
+"""Coefficient learning through the synthetic PA: the fused kernel step, the
+autograd step and the plain-ops autograd step against the FP64 chain."""
+import numpy as np
+import pytest
+
+from paper_1612_09001_amd import signals
+
+pytestmark = pytest.mark.gpu
+
+ORDERS = ([1, 3, 5, 7], [1, 3, 5, 7])
+L = 6
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+def _data(torch, rows, n, cid=5):
+    x = np.stack([signals.ofdm_16qam(n, config_id=cid, stream_id=r) for r in range(rows)])
+    return x, torch.from_numpy(x).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def test_fused_gradient_matches_fp64_chain(torch, orc):
+    import oracle.pa as opa
+    from paper_1612_09001_amd.train import FusedTrainer
+
+    x, xd = _data(torch, 3, 5000)
+    h = signals.aph_coeffs(*ORDERS, L, config_id=50)       # away from the optimum
+    tr = FusedTrainer(xd, *ORDERS, L, h, lr=0.0)
+    loss = tr.step()
+    torch.cuda.synchronize()
+    E, g = opa.chain_loss_and_gradient(orc, x, ORDERS, L, h)
+    assert abs(float(loss.item()) - E) <= 1e-5 * E
+    assert _rel(tr.gc.cpu().numpy(), g) <= 1e-4, _rel(tr.gc.cpu().numpy(), g)
+
+
+def test_three_paths_agree(torch):
+    from paper_1612_09001_amd.baselines import PlainTrainer
+    from paper_1612_09001_amd.train import AutogradTrainer, FusedTrainer
+
+    _, xd = _data(torch, 4, 8192)
+    h0 = signals.identity_coeffs(*ORDERS, L)
+    trs = [FusedTrainer(xd, *ORDERS, L, h0), AutogradTrainer(xd, *ORDERS, L, h0),
+           PlainTrainer(xd, *ORDERS, L, h0)]
+    hist = [[], [], []]
+    for _ in range(20):
+        for i, t in enumerate(trs):
+            hist[i].append(float(t.step().item()))
+    hist = np.array(hist)
+    assert np.all(np.abs(hist[1] - hist[0]) <= 1e-3 * hist[0])
+    assert np.all(np.abs(hist[2] - hist[0]) <= 1e-3 * hist[0])
+    assert hist[0, -1] < hist[0, 0]
+
+
+def test_config5_training_and_resume(torch):
+    """64 x 2^18 samples, identity start, 200 Adam steps; 100 + restore + 100
+    equals 200 straight, bitwise (deterministic reductions)."""
+    from paper_1612_09001_amd.train import FusedTrainer
+
+    _, xd = _data(torch, 64, 1 << 18)
+    h0 = signals.identity_coeffs(*ORDERS, L)
+    a = FusedTrainer(xd, *ORDERS, L, h0)
+    losses = [float(a.step().item()) for _ in range(200)]
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0], (losses[0], losses[-1])
+    b = FusedTrainer(xd, *ORDERS, L, h0)
+    for _ in range(100):
+        b.step()
+    state = b.state_dict()
+    c = FusedTrainer(xd, *ORDERS, L, h0)
+    c.load_state_dict(state)
+    for _ in range(100):
+        c.step()
+    assert torch.equal(c.coeffs, a.coeffs)
