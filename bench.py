@@ -1,18 +1,21 @@
 #!/usr/bin/env python3
-"""Throughput benchmark of the APH predistorter forward apply on one MI355X.
+"""Benchmark of the APH predistorter on one MI355X.
 
-Workload (default): one stream of N = 2^24 complex64 OFDM-like samples (16-QAM
+Headline workload: one stream of N = 2^24 complex64 OFDM-like samples (16-QAM
 on 1200 of 2048 subcarriers, RMS 0.25), odd orders {1,3,5,7} in the main and
 the conjugate branch, L = 4 taps, DC term; FP32 arithmetic.  One step = one
-forward apply of the whole stream (every step of Eq. 1 / Algorithm 1), on
+forward apply of the whole stream (every step of Eq. 1 / Algorithm 1) on
 inputs already resident in HBM.  Input/output buffers rotate over >= 2 GiB so
 the 256 MB last-level cache cannot serve repeated steps.
 
-Prints ONE JSON line with the throughput, the HBM roofline of the kernel
-(algorithmic bytes / kernel time, timed with HIP events on the launch stream)
-and the FP64 oracle timed on the host (which also gates accuracy).
+Prints ONE JSON line: throughput, the HBM roofline of the kernel (algorithmic
+bytes / kernel time from HIP events on the launch stream), the FP64 oracle
+timed on the host (which also gates accuracy) and, under "secondary", the
+other workloads: the two-carrier N = 2^26 stream (orders to 9, L = 8), the
+256-stream batch (persistent launch vs per-stream launches) and the
+coefficient-learning step (fused kernels vs autograd vs plain-ops autograd).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--main-only]
 """
 from __future__ import annotations
 
@@ -22,6 +25,7 @@ import json
 import os
 import sys
 import time
+import traceback
 
 import numpy as np
 
@@ -30,9 +34,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DPD Msamples/s + % HBM roofline at NMSE≤-110 dB vs oracle; grad-step time"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_SAMPLE = 16          # 8 B complex64 read + 8 B written
+VALU_FP32_PEAK_TFLOPS = 157.3      # published (packed FP32); non-packed issue: 78.6
+VALU_FP32_NONPACKED_TFLOPS = 78.6
+BYTES_PER_SAMPLE = 16              # 8 B complex64 read + 8 B written
 ROTATE_BYTES = 2 << 30
-PMC_FILE = os.path.join(ROOT, "profiles", "dpd_fwd_n2p24_P7_L4_traffic.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "dpd_fwd_n2p24_P7_L4_pmc.txt")
 KERNEL_SOURCES = ["paper_1612_09001_amd/csrc/dpd_fwd_kernels.h",
                   "paper_1612_09001_amd/csrc/dpd_internal.h"]
 
@@ -46,22 +52,29 @@ def kernel_hash() -> str:
 
 
 def traffic_from_profile(n: int):
-    """HBM bytes per launch from committed rocprofv3 --pmc counters, scaled by
-    the same counters read on a plain copy of known size; null when the
-    kernel sources changed since the counters were taken."""
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter read on a plain
+    copy of known size); None when the kernel sources changed since then."""
     try:
+        kv = {}
         with open(PMC_FILE) as f:
-            d = json.load(f)
-    except (OSError, ValueError):
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+    except OSError:
         return None
-    if d.get("kernel_hash") != kernel_hash() or d.get("n") != n:
+    if kv.get("kernel_sources_sha256_16") != kernel_hash() or kv.get("n") != str(n):
         return None
-    return d.get("traffic_bytes_per_launch")
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(x_host, z_gpu, mo, co, L, h):
-    """FP64 oracle on the host cores over the same stream (the whole config-2
-    workload, median of 3); also gates the GPU output against it."""
+    """FP64 oracle on the host cores over the whole headline workload (median
+    of 3); also gates the GPU output against it."""
     import oracle
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from metrics import max_rel, nmse_db
@@ -79,22 +92,150 @@ def cpu_baseline(x_host, z_gpu, mo, co, L, h):
     acc["pass"] = bool(acc["nmse_db"] <= -110.0 and acc["max_rel"] <= 2e-5)
     base = {"value": round(n / t / 1e6, 3), "unit": "Msamples/s", "cores": orc.threads(),
             "kind": "oracle",
-            "sample": "whole workload: %d samples, FP64 C oracle (gcc -O2, OpenMP), median of 3" % n}
+            "sample": "whole headline workload: %d samples through the FP64 C oracle "
+                      "(gcc -O2, OpenMP), median of 3" % n}
     return base, acc
+
+
+def _rotating(torch, x_host, total_bytes=ROTATE_BYTES):
+    n = x_host.size
+    nbuf = max(2, total_bytes // (2 * 8 * n))
+    xs = [torch.from_numpy(x_host).cuda() for _ in range(nbuf)]
+    zs = [torch.empty_like(xs[0]) for _ in range(nbuf)]
+    return xs, zs
+
+
+def _time_launches(torch, launch, nbuf, steps, warmup):
+    """Back-to-back launches between one pair of HIP events on the launch
+    stream (torch's current stream); returns wall seconds and mean ms per
+    launch (kernel time plus the inter-launch gap of a busy queue)."""
+    for i in range(warmup):
+        launch(i % nbuf)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for i in range(steps):
+        launch(i % nbuf)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1) / steps
+
+
+def leg_config3(torch, dpd, signals, steps=50):
+    """N = 2^26 two-carrier stream, orders {1..9} both branches, L = 8."""
+    orders = [1, 3, 5, 7, 9]
+    L, n = 8, 1 << 26
+    x_host = signals.two_carrier(n, config_id=3)
+    h = signals.aph_coeffs(orders, orders, L, config_id=3)
+    plan = dpd.Plan(orders, orders, L, h)
+    xs, zs = _rotating(torch, x_host)
+    st = dpd.current_stream()
+    ptrs = [(a.data_ptr(), b.data_ptr()) for a, b in zip(xs, zs)]
+    wall, kmean = _time_launches(
+        torch, lambda i: dpd.dpd_apply(plan.handle, st, ptrs[i][0], ptrs[i][1], n), len(xs), steps, 50)
+    flops = 8 * len(orders) * L + 3           # widely-linear FIR + |x|^2 per sample
+    tfl = flops * n / (kmean * 1e-3) / 1e12
+    gbs = BYTES_PER_SAMPLE * n / (kmean * 1e-3) / 1e9
+    del xs, zs
+    return {"workload": "two-carrier N=2^26, orders {1,3,5,7,9} main+conj, L=8, DC",
+            "msamples_per_s": round(n * steps / wall / 1e6, 1), "kernel_ms": round(kmean, 4),
+            "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "valu_tflops": round(tfl, 2), "flops_per_sample": flops,
+            "valu_frac_nonpacked": round(tfl / VALU_FP32_NONPACKED_TFLOPS, 4),
+            "valu_frac_published": round(tfl / VALU_FP32_PEAK_TFLOPS, 4), "tune": plan.get_tune()}
+
+
+def leg_config4(torch, dpd, signals, reps=20):
+    """256 streams, lengths U[2^14, 2^20], own coefficients, P_max in {5,7,9},
+    L in {2..8}: one persistent launch (graph-replayed) vs 256 launches."""
+    from paper_1612_09001_amd import autotune, batch
+
+    wl = batch.BatchWorkload(signals.batch_specs(), config_id=4)
+    tune, b = autotune.tune_batch(wl)
+    total = wl.samples()
+    t_direct = autotune.time_us(b.apply, iters=reps)
+    t_each = autotune.time_us(b.apply_each, iters=reps)
+    g = torch.cuda.CUDAGraph()
+    b.apply()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        b.apply()
+    t_graph = autotune.time_us(g.replay, iters=reps)
+    ge = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(ge):
+        b.apply_each()
+    t_graph_each = autotune.time_us(ge.replay, iters=reps)
+    gbs = BYTES_PER_SAMPLE * total / (t_graph * 1e-6) / 1e9
+    return {"workload": "256 streams, n~U[2^14,2^20] (seeded), P_max in {5,7,9}, L in {2..8}, conj+DC",
+            "samples": total, "tune": tune, "tiles_blocks": list(b.info()),
+            "persistent_graph_us": round(t_graph, 1), "persistent_us": round(t_direct, 1),
+            "per_stream_launches_us": round(t_each, 1), "per_stream_graph_us": round(t_graph_each, 1),
+            "msamples_per_s": round(total / t_graph, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "speedup_vs_per_stream": round(t_each / t_graph, 2),
+            "speedup_vs_per_stream_graph": round(t_graph_each / t_graph, 2)}
+
+
+def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
+    """64 x 2^18 samples, DPD orders {1,3,5,7} both branches, L = 6, identity
+    start, synthetic PA, loss mean|y/10 - x|^2, Adam lr 1e-3."""
+    from paper_1612_09001_amd.baselines import PlainTrainer
+    from paper_1612_09001_amd.train import AutogradTrainer, FusedTrainer
+
+    orders, L, rows, n = [1, 3, 5, 7], 6, 64, 1 << 18
+    x = np.stack([signals.ofdm_16qam(n, config_id=5, stream_id=r) for r in range(rows)])
+    xd = torch.from_numpy(x).cuda()
+    h0 = signals.identity_coeffs(orders, orders, L)
+
+    def run(tr, k):
+        ms, losses = [], []
+        for _ in range(k):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            loss = tr.step()
+            e1.record()
+            losses.append(loss.clone())
+            ms.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = [a.elapsed_time(b) for a, b in ms]
+        return ms, [float(v.item()) for v in losses]
+
+    fused_ms, fused_loss = run(FusedTrainer(xd, orders, orders, L, h0), steps)
+    auto_ms, auto_loss = run(AutogradTrainer(xd, orders, orders, L, h0), plain_steps)
+    plain_ms, plain_loss = run(PlainTrainer(xd, orders, orders, L, h0), plain_steps)
+    k = min(plain_steps, steps)
+    agree = float(np.max(np.abs(np.array(plain_loss[:k]) - np.array(fused_loss[:k])) /
+                         np.array(fused_loss[:k])))
+    med = lambda v: float(np.median(v[10:] if len(v) > 12 else v[2:]))
+    return {"workload": "64x2^18 OFDM-like, DPD {1,3,5,7} main+conj L=6, synthetic PA, Adam 1e-3",
+            "grad_step_ms_fused": round(med(fused_ms), 4),
+            "grad_step_ms_autograd_dpdfunction": round(med(auto_ms), 4),
+            "grad_step_ms_plain_ops_autograd": round(med(plain_ms), 4),
+            "speedup_vs_plain_ops": round(med(plain_ms) / med(fused_ms), 2),
+            "loss_db_step0": round(10 * np.log10(fused_loss[0]), 2),
+            "loss_db_final": round(10 * np.log10(fused_loss[-1]), 2), "steps": steps,
+            "plain_vs_fused_loss_rel_max_first_%d" % k: float("%.3g" % agree)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    # the GPU clocks need ~500 launches (~30 ms) of load to settle
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--log2n", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle leg")
-    ap.add_argument("--tune", default="", help="S,LDS[,GRID_MULT] override, e.g. 2,1,8")
+    ap.add_argument("--main-only", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--tune", default="", help="S,LDS[,GRID_MULT] override, e.g. 8,1,16")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain device copy of the same bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(see DESIGN.md for how the path would shard)" % args.gpus, file=sys.stderr)
+              "(DESIGN.md describes how the path would shard)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -109,36 +250,21 @@ def main():
     if args.tune:
         vals = [int(v) for v in args.tune.split(",")]
         plan.set_tune(samples_per_thread=vals[0], stage_lds=vals[1],
-                      grid_mult=vals[2] if len(vals) > 2 else 8)
+                      grid_mult=vals[2] if len(vals) > 2 else 16)
     tune = plan.get_tune()
 
-    nbuf = max(2, ROTATE_BYTES // (2 * 8 * n))
-    xs = [torch.from_numpy(x_host).cuda() for _ in range(nbuf)]
-    zs = [torch.empty_like(xs[0]) for _ in range(nbuf)]
+    xs, zs = _rotating(torch, x_host)
+    nbuf = len(xs)
     stream = dpd.current_stream()
     ptrs = [(a.data_ptr(), b.data_ptr()) for a, b in zip(xs, zs)]
     handle = plan.handle
+    if args.calibrate_copy:
+        zs[0].copy_(xs[0])
+        torch.cuda.synchronize()
 
-    def step(i):
-        pi, po = ptrs[i % nbuf]
-        dpd.dpd_apply(handle, stream, pi, po, n)
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record()
-        step(i)
-        ends[i].record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    kern_ms = float(np.mean([s.elapsed_time(e) for s, e in zip(starts, ends)]))
+    wall, kern_ms = _time_launches(
+        torch, lambda i: dpd.dpd_apply(handle, stream, ptrs[i][0], ptrs[i][1], n), nbuf,
+        args.steps, args.warmup)
     ms_per_step = wall * 1e3 / args.steps
     value = n * args.steps / wall / 1e6
     achieved = BYTES_PER_SAMPLE * n / (kern_ms * 1e-3) / 1e9
@@ -165,9 +291,21 @@ def main():
                      "kernel_ms": round(kern_ms, 5),
                      "algorithmic_bytes_per_launch": BYTES_PER_SAMPLE * n},
     }
+    z_last = zs[(args.steps - 1) % nbuf]
+    if not args.main_only:
+        del xs
+        sec = {}
+        for name, fn in (("config3", leg_config3), ("config4", leg_config4),
+                         ("config5", leg_config5)):
+            try:
+                sec[name] = fn(torch, dpd, signals)
+            except Exception as e:  # a failing secondary leg must not hide the headline
+                traceback.print_exc(file=sys.stderr)
+                sec[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+            torch.cuda.empty_cache()
+        out["secondary"] = sec
     if not args.no_cpu:
-        z_gpu = zs[(args.steps - 1) % nbuf].cpu().numpy()
-        base, acc = cpu_baseline(x_host, z_gpu, mo, co, L, h)
+        base, acc = cpu_baseline(x_host, z_last.cpu().numpy(), mo, co, L, h)
         out["cpu_baseline"] = base
         out["accuracy"] = acc
     print(json.dumps(out), flush=True)
