@@ -235,7 +235,7 @@ dpd_tune default_tune()
     t.samples_per_thread = 8;
     t.stage_lds = 1;
     t.block = kBlock;
-    t.grid_mult = 16;   // capped at the resident-block limit of the kernel
+    t.grid_mult = 2;    // persistent blocks per CU (capped at the resident limit)
     return t;
 }
 

@@ -89,6 +89,47 @@ __device__ __forceinline__ void fir_outputs(const float (&a)[S + L - 1], const f
     }
 }
 
+// Same FIR with every coefficient in registers (coef: the whole table,
+// 4*L*NI + 2 floats): no scalar operands, so no extra moves or scalar
+// register pressure.  Used when the table is small enough to keep resident.
+template <int NI, int L, int S>
+__device__ __forceinline__ void fir_outputs_reg(const float (&a)[S + L - 1], const float (&b)[S + L - 1],
+                                                const float (&s)[S + L - 1],
+                                                const float (&coef)[4 * L * NI + 2], float (&zr)[S],
+                                                float (&zi)[S])
+{
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        zr[i] = coef[4 * L * NI];
+        zi[i] = coef[4 * L * NI + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        const float *Mk = coef + 4 * NI * k;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const int w = i + (L - 1) - k;
+            float w00 = Mk[4 * (NI - 1) + 0], w01 = Mk[4 * (NI - 1) + 1];
+            float w10 = Mk[4 * (NI - 1) + 2], w11 = Mk[4 * (NI - 1) + 3];
+#pragma unroll
+            for (int j = NI - 2; j >= 0; --j) {
+                w00 = __builtin_fmaf(w00, s[w], Mk[4 * j + 0]);
+                w01 = __builtin_fmaf(w01, s[w], Mk[4 * j + 1]);
+                w10 = __builtin_fmaf(w10, s[w], Mk[4 * j + 2]);
+                w11 = __builtin_fmaf(w11, s[w], Mk[4 * j + 3]);
+            }
+            zr[i] = __builtin_fmaf(w00, a[w], zr[i]);
+            zr[i] = __builtin_fmaf(w01, b[w], zr[i]);
+            zi[i] = __builtin_fmaf(w10, a[w], zi[i]);
+            zi[i] = __builtin_fmaf(w11, b[w], zi[i]);
+        }
+    }
+}
+
+// Coefficient tables up to this many floats stay in registers in the
+// streaming kernel (larger ones are read as scalar operands).
+constexpr int kRegCoefMax = 96;
+
 template <int W>
 __device__ __forceinline__ void split_window(const float2 (&win)[W], float (&a)[W], float (&b)[W],
                                              float (&s)[W])
@@ -188,20 +229,19 @@ __device__ __forceinline__ void wave_lds_order()
 // the waves of the grid work on adjacent chunks of C = 64*S samples (wave g
 // takes chunks g, g + nw, g + 2 nw, ... of the flattened rows), so the whole
 // chip sweeps memory in order.  Per chunk:
-//   * the next D chunks are already in flight (register prefetch ring); every
-//     load instruction reads 1 KiB of contiguous memory (lane l, part i ->
-//     the 16 bytes at sample 2*(l + 64 i)), plus one broadcast 8-byte load per
-//     lane for the L-1 halo samples before the chunk (zeros at a row start,
-//     the caller's history before row 0);
+//   * the next chunk is already in flight (register prefetch); every
+//     load instruction is a nontemporal read of 1 KiB of contiguous memory
+//     (lane l, part i -> the 16 bytes at sample 2*(l + 64 i)); the L-1 halo
+//     samples before the chunk come through the scalar cache (zeros at a row
+//     start, the caller's history before row 0);
 //   * samples and |x|^2 go to a wave-private LDS buffer laid out with one pad
 //     slot after every S samples (odd lane stride: conflict-free window reads);
 //     each lane reads its S+L-1 consecutive-sample window back, filters and
 //     stores 16-byte outputs.
-// The loop body has no divergent global accesses and the prefetch is
-// unconditional (past the end it re-reads the wave's last chunk, which the L2
-// still holds), so the compiler's counter waits stay exact.  The partial last
-// chunk of each row (when C does not divide n) is handled after the loop with
-// guarded accesses.  No block-wide barrier after the coefficient staging.
+// The loop body has no divergent global accesses and no conditional loads, so
+// the compiler's counter waits stay exact.  The partial last chunk of each row
+// (when C does not divide n) is handled after the loop with guarded accesses.
+// No block-wide barrier after the coefficient staging.
 template <int S>
 struct ChunkRegs {
     float4 v[S / 2];
@@ -220,28 +260,39 @@ struct PadLayout {
     }
 };
 
-template <int NI, int L, int S, int D>
+template <int NI, int L, int S>
 __global__ void __launch_bounds__(kBlock) fwd_stream_kernel(FwdParams p)
 {
     static_assert(S % 2 == 0, "S must be even (16-byte loads and stores)");
-    static_assert(D >= 1 && D <= 3, "prefetch depth 1..3");
     constexpr int C = 64 * S;
     constexpr int W = S + L - 1;
     constexpr int NV = S / 2;
     constexpr int WAVES = kBlock / 64;
     using PL = PadLayout<L, S>;
     constexpr int HS = L - 1;                        // halo samples
-    __shared__ float ctop[4 * L];
+    constexpr int NC = 4 * L * NI + 2;               // coefficient table floats
+    constexpr bool REG = NC <= kRegCoefMax;          // whole table in registers
+    __shared__ float ctab[REG ? NC : 4 * L];
     __shared__ __align__(16) float2 xs[WAVES][PL::SLOTS];
     __shared__ __align__(16) float ss[WAVES][PL::SLOTS];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform per wave
-    if (tid < 4 * L) ctop[tid] = p.M[(tid >> 2) * 4 * NI + 4 * (NI - 1) + (tid & 3)];
+    if constexpr (REG) {
+        if (tid < NC) ctab[tid] = p.M[tid];
+    } else {
+        if (tid < 4 * L) ctab[tid] = p.M[(tid >> 2) * 4 * NI + 4 * (NI - 1) + (tid & 3)];
+    }
     __syncthreads();
     float top[4 * L];
+    float coef[REG ? NC : 1];
+    if constexpr (REG) {
 #pragma unroll
-    for (int e = 0; e < 4 * L; ++e) top[e] = ctop[e];
+        for (int e = 0; e < NC; ++e) coef[e] = ctab[e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 4 * L; ++e) top[e] = ctab[e];
+    }
     const cfloat *M = as_const(p.M);
 
     float2 *X = xs[wv];
@@ -256,10 +307,30 @@ __global__ void __launch_bounds__(kBlock) fwd_stream_kernel(FwdParams p)
     float2 hist_v = make_float2(0.f, 0.f);
     if (HS > 0 && p.hist != nullptr) hist_v = p.hist[hl];
 
-    // raw sample for halo sample hl - HS of the chunk starting at t0 (clamped)
+    // raw sample for halo sample hl - HS of the chunk starting at t0: the HS
+    // samples sit at a uniform address, so they come through the scalar cache.
+    // At a row start (t0 < HS) nothing is read; the value is replaced at use.
     auto halo_raw = [&](int64_t row, int64_t t0) {
-        const int64_t m = t0 - HS + hl;
-        return p.in[row * p.ld + (m >= 0 ? m : 0)];
+        float2 r = make_float2(0.f, 0.f);
+        if (HS > 0 && t0 >= HS) {
+            const cfloat *hp = as_const(reinterpret_cast<const float *>(p.in + row * p.ld + t0 - HS));
+            r = make_float2(hp[0], hp[1]);
+#pragma unroll
+            for (int k = 1; k < (HS > 0 ? HS : 1); ++k)
+                if (hl == k) r = make_float2(hp[2 * k], hp[2 * k + 1]);
+        }
+        return r;
+    };
+    // The same for a full chunk (row length >= C > HS): always read, from the
+    // row start when t0 < HS, so the loop issues the same loads on every trip.
+    auto halo_raw_full = [&](int64_t row, int64_t t0) {
+        const int64_t off = t0 >= HS ? t0 - HS : 0;
+        const cfloat *hp = as_const(reinterpret_cast<const float *>(p.in + row * p.ld + off));
+        float2 r = make_float2(hp[0], hp[1]);
+#pragma unroll
+        for (int k = 1; k < (HS > 0 ? HS : 1); ++k)
+            if (hl == k) r = make_float2(hp[2 * k], hp[2 * k + 1]);
+        return r;
     };
 
     // samples -> LDS, windows -> registers, filter
@@ -294,7 +365,10 @@ __global__ void __launch_bounds__(kBlock) fwd_stream_kernel(FwdParams p)
             b[w] = v.y;
             s[w] = SX[q];
         }
-        fir_outputs<NI, L, S>(a, b, s, top, M, zr, zi);
+        if constexpr (REG)
+            fir_outputs_reg<NI, L, S>(a, b, s, coef, zr, zi);
+        else
+            fir_outputs<NI, L, S>(a, b, s, top, M, zr, zi);
     };
 
     // Store the S outputs of every lane of a full chunk.  S = 2: each lane's
@@ -328,53 +402,59 @@ __global__ void __launch_bounds__(kBlock) fwd_stream_kernel(FwdParams p)
         // chunk c <-> (row, k); advancing by nw chunks without dividing
         const int64_t dr = nw / tpr, dk = nw - (nw / tpr) * tpr;
         struct Cur {
-            int64_t c, row, k;
+            int64_t row, k;
         };
-        const int64_t c_last = gw + ((total - 1 - gw) / nw) * nw;
-        auto advance = [&](Cur &u) {
-            if (u.c == c_last) return;       // clamp: keep re-reading the last chunk
-            u.c += nw;
+        auto next = [&](Cur u) {
             u.row += dr;
             u.k += dk;
             if (u.k >= tpr) {
                 u.k -= tpr;
                 ++u.row;
             }
+            return u;
         };
         auto load_full = [&](ChunkRegs<S> &buf, const Cur &u) {
             const int64_t t0 = u.k * C;
             const float4 *x4 = reinterpret_cast<const float4 *>(p.in + u.row * p.ld + t0);
 #pragma unroll
-            for (int i = 0; i < NV; ++i) buf.v[i] = x4[lane + 64 * i];
-            buf.h = halo_raw(u.row, t0);
-        };
-        ChunkRegs<S> ring[D + 1];
-        Cur pos[D + 1];
-        Cur pf;                                       // prefetch cursor
-        pf.c = gw;
-        pf.row = gw / tpr;
-        pf.k = gw - pf.row * tpr;
-#pragma unroll
-        for (int u = 0; u < D; ++u) {
-            pos[u] = pf;
-            load_full(ring[u], pf);
-            advance(pf);
-        }
-        for (;;) {
-#pragma unroll
-            for (int u = 0; u <= D; ++u) {
-                const int nxt = (u + D) % (D + 1);
-                pos[nxt] = pf;
-                load_full(ring[nxt], pf);
-                advance(pf);
-                const Cur cur = pos[u];
-                float zr[S], zi[S];
-                filter_chunk(ring[u], cur.row, cur.k * C, zr, zi);
-                store_chunk(p.out + cur.row * p.ld, cur.k * C, zr, zi);
-                if (cur.c == c_last) goto done;
+            for (int i = 0; i < NV; ++i) {
+                // read once: nontemporal (streaming) loads
+                const v4f t = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(x4) + lane + 64 * i);
+                buf.v[i] = make_float4(t.x, t.y, t.z, t.w);
             }
+            buf.h = halo_raw_full(u.row, t0);
+        };
+        auto step = [&](const ChunkRegs<S> &buf, const Cur &u) {
+            float zr[S], zi[S];
+            filter_chunk(buf, u.row, u.k * C, zr, zi);
+            store_chunk(p.out + u.row * p.ld, u.k * C, zr, zi);
+        };
+        // Two chunks per trip with the next one always in flight; the loop
+        // body is straight-line code (exact counter waits) and the last one
+        // or two chunks are peeled off, so nothing is read past the run.
+        int64_t left = (total - 1 - gw) / nw + 1;    // chunks of this wave
+        Cur cur;
+        cur.row = gw / tpr;
+        cur.k = gw - cur.row * tpr;
+        ChunkRegs<S> A, B;
+        load_full(A, cur);
+        for (; left >= 3; left -= 2) {
+            const Cur c1 = next(cur);
+            load_full(B, c1);
+            step(A, cur);
+            const Cur c2 = next(c1);
+            load_full(A, c2);
+            step(B, c1);
+            cur = c2;
         }
-    done:;
+        if (left == 2) {
+            const Cur c1 = next(cur);
+            load_full(B, c1);
+            step(A, cur);
+            step(B, c1);
+        } else {
+            step(A, cur);
+        }
     }
 
     // ---- the partial last chunk of each row (when C does not divide n)
@@ -402,10 +482,6 @@ __global__ void __launch_bounds__(kBlock) fwd_stream_kernel(FwdParams p)
     }
 }
 
-template <int S>
-struct PrefetchDepth {
-    static constexpr int value = S == 2 ? 3 : (S == 4 ? 2 : 1);
-};
 
 int num_cus();
 
@@ -419,7 +495,7 @@ hipError_t launch_fwd(const FwdParams &p, hipStream_t stream, int grid_mult)
         // persistent grid would double the tail)
         static const int occ = [] {
             int o = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, fwd_stream_kernel<NI, L, S, PrefetchDepth<S>::value>, kBlock,
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, fwd_stream_kernel<NI, L, S>, kBlock,
                                                              0) != hipSuccess || o < 1)
                 o = 1;
             return o;
@@ -427,7 +503,7 @@ hipError_t launch_fwd(const FwdParams &p, hipStream_t stream, int grid_mult)
         const int64_t want = (int64_t)num_cus() * (grid_mult < occ ? grid_mult : occ);
         const int64_t need = (p.total_tiles + kBlock / 64 - 1) / (kBlock / 64);   // >= 1 wave per chunk
         grid = need < want ? need : want;
-        hipLaunchKernelGGL((fwd_stream_kernel<NI, L, S, PrefetchDepth<S>::value>), dim3((uint32_t)grid),
+        hipLaunchKernelGGL((fwd_stream_kernel<NI, L, S>), dim3((uint32_t)grid),
                            dim3(kBlock), 0,
                            stream, p);
     } else {
