@@ -262,9 +262,17 @@ def main():
         zs[0].copy_(xs[0])
         torch.cuda.synchronize()
 
+    # Warm the clocks with the one-shot variant of the filter (a different
+    # kernel symbol), so a profiler's per-kernel average of the timed kernel
+    # covers exactly the timed launches.
+    plan.set_tune(samples_per_thread=tune["samples_per_thread"], stage_lds=0)
+    for i in range(args.warmup):
+        dpd.dpd_apply(handle, stream, ptrs[i % nbuf][0], ptrs[i % nbuf][1], n)
+    plan.set_tune(samples_per_thread=tune["samples_per_thread"], stage_lds=tune["stage_lds"],
+                  grid_mult=tune["grid_mult"])
     wall, kern_ms = _time_launches(
         torch, lambda i: dpd.dpd_apply(handle, stream, ptrs[i][0], ptrs[i][1], n), nbuf,
-        args.steps, args.warmup)
+        args.steps, 1)
     ms_per_step = wall * 1e3 / args.steps
     value = n * args.steps / wall / 1e6
     achieved = BYTES_PER_SAMPLE * n / (kern_ms * 1e-3) / 1e9
