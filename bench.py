@@ -169,13 +169,46 @@ def leg_config4(torch, dpd, signals, reps=20):
         b.apply_each()
     t_graph_each = autotune.time_us(ge.replay, iters=reps)
     gbs = BYTES_PER_SAMPLE * total / (t_graph * 1e-6) / 1e9
+    # widely-linear FIR + |x|^2 per sample, per stream (both branches hold orders 1..P_max)
+    flops = sum(n * (8 * ((pmax + 1) // 2) * L + 3) for n, pmax, L in wl.specs)
+    t_hbm = BYTES_PER_SAMPLE * total / (HBM_PEAK_GBS * 1e9) * 1e6
+    t_valu = flops / (VALU_FP32_NONPACKED_TFLOPS * 1e12) * 1e6
     return {"workload": "256 streams, n~U[2^14,2^20] (seeded), P_max in {5,7,9}, L in {2..8}, conj+DC",
-            "samples": total, "tune": tune, "tiles_blocks": list(b.info()),
+            "samples": total, "tune": tune, "chunks_blocks": list(b.info()),
             "persistent_graph_us": round(t_graph, 1), "persistent_us": round(t_direct, 1),
             "per_stream_launches_us": round(t_each, 1), "per_stream_graph_us": round(t_graph_each, 1),
             "msamples_per_s": round(total / t_graph, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "flops_per_sample": round(flops / total, 1),
+            "valu_frac_nonpacked": round(flops / (t_graph * 1e-6) / 1e12 / VALU_FP32_NONPACKED_TFLOPS, 4),
+            "bound_us": round(max(t_hbm, t_valu), 1), "bound_frac": round(max(t_hbm, t_valu) / t_graph, 4),
             "speedup_vs_per_stream": round(t_each / t_graph, 2),
             "speedup_vs_per_stream_graph": round(t_graph_each / t_graph, 2)}
+
+
+def leg_backward(torch, dpd, signals, steps=50):
+    """Adjoint of the headline forward (N = 2^24, orders {1,3,5,7} both
+    branches, L = 4): input and coefficient gradients in one call."""
+    orders, L, n = [1, 3, 5, 7], 4, 1 << 24
+    h = signals.aph_coeffs(orders, orders, L, config_id=1)
+    plan = dpd.Plan(orders, orders, L, h)
+    x = torch.from_numpy(signals.ofdm_16qam(n, config_id=1)).cuda()
+    g = torch.from_numpy(signals.ofdm_16qam(n, config_id=1, stream_id=1)).cuda()
+    gx = torch.empty_like(x)
+    gc = torch.empty(plan.K, dtype=torch.complex64, device="cuda")
+    wsb = dpd.dpd_backward_ws_size(plan.handle, 1, n)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
+    st = dpd.current_stream()
+    wall, kmean = _time_launches(
+        torch, lambda i: dpd.dpd_backward(plan.handle, st, 0, x.data_ptr(), g.data_ptr(), gx.data_ptr(),
+                                          gc.data_ptr(), 1, n, n, ws.data_ptr(), wsb), 1, steps, 20)
+    ni = (orders[-1] + 1) // 2
+    # dx: transposed filter 8*NI*L + basis Jacobian ~12*NI; dcoef: outer products 8*NI*L + basis 2*NI
+    flops = 16 * ni * L + 14 * ni
+    nbytes = 24 * n                         # x and G read, dx written
+    return {"workload": "adjoint of the headline: N=2^24, orders {1,3,5,7} main+conj, L=4; dx and dcoef",
+            "kernel_ms": round(kmean, 4), "msamples_per_s": round(n / (kmean * 1e-3) / 1e6, 1),
+            "hbm_frac": round(nbytes / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "flops_per_sample": flops,
+            "valu_frac_nonpacked": round(flops * n / (kmean * 1e-3) / 1e12 / VALU_FP32_NONPACKED_TFLOPS, 4)}
 
 
 def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
@@ -304,7 +337,7 @@ def main():
         del xs
         sec = {}
         for name, fn in (("config3", leg_config3), ("config4", leg_config4),
-                         ("config5", leg_config5)):
+                         ("backward", leg_backward), ("config5", leg_config5)):
             try:
                 sec[name] = fn(torch, dpd, signals)
             except Exception as e:  # a failing secondary leg must not hide the headline

@@ -166,8 +166,10 @@ typedef struct dpd_stream_desc {
     const void *coeffs_dev;  /* device, K complex64 in section 2.2 layout    */
 } dpd_stream_desc;
 
-/* dpd_batch_create -- validate the descriptors, build the tile table (tiles
- * ordered most expensive first), upload it, and size the persistent grid.
+/* dpd_batch_create -- validate the descriptors, cut every stream into chunks
+ * of 64*S samples (S = tune->samples_per_thread; a stream's last chunk may be
+ * shorter), list them most expensive class first, upload the list (32 bytes
+ * per chunk), and size the persistent grid.
  * `tune` may be NULL for the default launch shape.  The descriptor pointers
  * must stay valid for the life of the batch.  Synchronous. */
 dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_streams, const dpd_tune *tune,
@@ -175,15 +177,15 @@ dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_streams, cons
 
 /* dpd_batch_apply -- one persistent launch (plus one coefficient-precombine
  * launch) on `stream`.  Allocates nothing, never synchronizes the host and
- * may be captured in a hipGraph; the work counter resets itself at the end of
- * each launch.  Calls that overlap in time on one batch race. */
+ * may be captured in a hipGraph (there is no device counter to reset).  Calls that overlap in time on one batch race. */
 dpd_status dpd_batch_apply(dpd_batch *batch, void *stream);
 
 /* dpd_batch_apply_each -- reference schedule: one launch per stream with the
  * same kernels as dpd_apply (for comparison against the persistent form). */
 dpd_status dpd_batch_apply_each(dpd_batch *batch, void *stream);
 
-/* dpd_batch_info -- number of tiles and persistent blocks of the batch. */
+/* dpd_batch_info -- number of chunks (full and ragged) in the persistent
+ * launch and its number of blocks. */
 dpd_status dpd_batch_info(const dpd_batch *batch, int64_t *n_tiles, int32_t *n_blocks);
 
 /* dpd_batch_destroy -- waits for the device, then frees the batch. */

@@ -1,8 +1,9 @@
 """Batched multi-stream apply (many antennas, uneven lengths, own coefficients).
 
 ``Batch`` wraps ``dpd_batch_create`` / ``dpd_batch_apply``: one coefficient
-precombine launch plus one persistent launch for all streams, graph-capturable
-(no allocation, no host synchronization, self-resetting work counter).
+precombine launch, one persistent launch over the full chunks of all streams
+and one small launch for their ragged ends; graph-capturable (no allocation,
+no host synchronization, no device state carried between calls).
 ``BatchWorkload`` builds the multi-antenna workload in two device arenas
 (inputs, outputs) with 16-byte aligned stream offsets plus one coefficient
 arena, from the seeded generators in ``signals``.

@@ -20,13 +20,14 @@ struct dpd_batch {
     std::vector<dpd::CoefMap> maps;
     std::vector<int32_t> tab;
     std::vector<int32_t> fallback;       // streams run by separate launches
-    dpd::BatchStream *d_streams = nullptr;
-    dpd::BatchItem *d_items = nullptr;
+    dpd::BatchChunk *d_chunks = nullptr;  // full chunks, ragged chunks, idle entry
     dpd::BatchPrep *d_prep = nullptr;
     float *d_tables = nullptr;
-    unsigned int *d_counter = nullptr;
-    int64_t n_items = 0;
-    int grid = 0;
+    float2 *d_idle = nullptr;              // samples the idle entry points at
+    int64_t n_full = 0;
+    int64_t n_chunks = 0;
+    int grid = 0;        // blocks of the streaming kernel
+    int tail_grid = 0;   // blocks of the ragged-chunk kernel
     int sidx = 2;
     dpd_tune tune;
 };
@@ -92,11 +93,10 @@ static int batch_occupancy(int sidx)
 
 static void free_batch(dpd_batch *b)
 {
-    if (b->d_streams) (void)hipFree(b->d_streams);
-    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_chunks) (void)hipFree(b->d_chunks);
     if (b->d_prep) (void)hipFree(b->d_prep);
     if (b->d_tables) (void)hipFree(b->d_tables);
-    if (b->d_counter) (void)hipFree(b->d_counter);
+    if (b->d_idle) (void)hipFree(b->d_idle);
     delete b;
 }
 
@@ -147,9 +147,8 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
     b->sidx = t.samples_per_thread == 2 ? 0 : (t.samples_per_thread == 4 ? 1 : 2);
     b->n_streams = n_streams;
     b->desc.assign(desc, desc + n_streams);
-    std::vector<BatchStream> streams(n_streams);
     std::vector<BatchPrep> prep(n_streams);
-    std::vector<BatchItem> items;
+    std::vector<int32_t> order;   // streams in the persistent kernel
     int64_t tab_total = 0;
     for (int32_t s = 0; s < n_streams; ++s) {
         const dpd_stream_desc &d = desc[s];
@@ -179,22 +178,11 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
         tab_total += (table_floats(map.L, map.NI) + 3) & ~3;
         const bool aligned = (uintptr_t)d.in % 16 == 0 && (uintptr_t)d.out % 16 == 0;
         const bool in_kernel = aligned && map.NI <= kBatchMaxNI && map.L <= kBatchMaxL;
-        streams[s].in = (const float2 *)d.in;
-        streams[s].out = (float2 *)d.out;
-        streams[s].n = d.n;
-        streams[s].tab = prep[s].tab;
-        streams[s].cls = in_kernel ? (map.NI - 1) * kBatchMaxL + (map.L - 1) : -1;
         if (!in_kernel) {
             b->fallback.push_back(s);
             continue;
         }
-        for (int64_t t0 = 0; t0 < d.n; t0 += kBatchItem) {
-            BatchItem it;
-            it.stream = s;
-            it.pad_ = 0;
-            it.t0 = t0;
-            items.push_back(it);
-        }
+        if (d.n > 0) order.push_back(s);
     }
     // no stream may write where another reads or writes
     for (int32_t s = 0; s < n_streams; ++s) {
@@ -210,34 +198,66 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
             }
         }
     }
-    if ((int64_t)items.size() >= (int64_t)1 << 30 || tab_total >= (int64_t)1 << 30) {
+    if (tab_total >= (int64_t)1 << 30) {
         free_batch(b);
         return DPD_EUNSUPPORTED;
     }
-    // most expensive items first: per-sample cost ~ NI * L, full items before
-    // the partial last item of a stream; ties keep stream order
-    auto cost = [&](const BatchItem &it) {
-        const CoefMap &m = b->maps[it.stream];
-        const int64_t len = std::min<int64_t>(kBatchItem, desc[it.stream].n - it.t0);
-        return (int64_t)m.NI * m.L * len;
+    // Streams most expensive class first (per-sample cost ~ NI * L), one class
+    // together, then stream order; their full chunks in that order, then the
+    // ragged last chunks in the same order, then the idle entry.
+    auto cls_of = [&](int32_t s) { return (b->maps[s].NI - 1) * kBatchMaxL + (b->maps[s].L - 1); };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        const int cx = b->maps[x].NI * b->maps[x].L, cy = b->maps[y].NI * b->maps[y].L;
+        return cx != cy ? cx > cy : cls_of(x) < cls_of(y);
+    });
+    const int64_t C = 64 * (int64_t)t.samples_per_thread;
+    std::vector<BatchChunk> chunks;
+    auto push = [&](int32_t s, int64_t t0, int64_t valid) {
+        const dpd_stream_desc &d = desc[s];
+        const CoefMap &m = b->maps[s];
+        BatchChunk c;
+        c.in = (const float2 *)d.in + t0;
+        c.out = (float2 *)d.out + t0;
+        c.tab = b->tab[s];
+        c.meta = batch_meta(cls_of(s), (int)std::min<int64_t>(t0, kBatchHalo),
+                            (table_floats(m.L, m.NI) + 3) / 4);
+        c.valid = (int32_t)valid;
+        c.pad_ = 0;
+        chunks.push_back(c);
     };
-    std::stable_sort(items.begin(), items.end(),
-                     [&](const BatchItem &a, const BatchItem &c) { return cost(a) > cost(c); });
-    b->n_items = (int64_t)items.size();
+    for (int32_t s : order)
+        for (int64_t t0 = 0; t0 + C <= desc[s].n; t0 += C) push(s, t0, C);
+    b->n_full = (int64_t)chunks.size();
+    for (int32_t s : order)
+        if (desc[s].n % C != 0) push(s, desc[s].n - desc[s].n % C, desc[s].n % C);
+    b->n_chunks = (int64_t)chunks.size();
     hipError_t e = hipGetDevice(&b->device);
-    if (e == hipSuccess) e = upload(&b->d_streams, streams);
-    if (e == hipSuccess) e = upload(&b->d_items, items);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_idle, (size_t)C * sizeof(float2));
+    if (e == hipSuccess) e = hipMemset(b->d_idle, 0, (size_t)C * sizeof(float2));
+    if (e == hipSuccess) {
+        BatchChunk idle;
+        idle.in = b->d_idle;
+        idle.out = b->d_idle;   // never written: the idle entry is only read
+        idle.tab = 0;
+        idle.meta = batch_meta(0, 0, 1);
+        idle.valid = (int32_t)C;
+        idle.pad_ = 0;
+        chunks.push_back(idle);
+        e = upload(&b->d_chunks, chunks);
+    }
     if (e == hipSuccess) e = upload(&b->d_prep, prep);
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_tables, std::max<int64_t>(tab_total, 4) * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, 2 * sizeof(unsigned int));
-    if (e == hipSuccess) e = hipMemset(b->d_counter, 0, 2 * sizeof(unsigned int));
+    // + 4 floats: the idle entry reads table floats 0..3
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_tables, (size_t)(tab_total + 4) * sizeof(float));
+    if (e == hipSuccess) e = hipMemset(b->d_tables, 0, (size_t)(tab_total + 4) * sizeof(float));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_batch(b);
         return e == hipErrorOutOfMemory ? DPD_ENOMEM : hip_fail(e);
     }
     const int64_t cap = (int64_t)num_cus() * std::min(t.grid_mult, batch_occupancy(b->sidx));
-    b->grid = (int)std::max<int64_t>(1, std::min<int64_t>(cap, b->n_items));
+    const int64_t waves = kBlock / 64;
+    b->grid = (int)std::min<int64_t>(cap, (b->n_full + waves - 1) / waves);
+    b->tail_grid = (int)std::min<int64_t>(cap, (b->n_chunks - b->n_full + waves - 1) / waves);
     *out = b;
     return DPD_OK;
 }
@@ -248,14 +268,13 @@ DPD_EXPORT dpd_status dpd_batch_apply(dpd_batch *b, void *stream)
     const hipStream_t st = (hipStream_t)stream;
     dpd_status s = batch_prep(b, st);
     if (s != DPD_OK) return s;
-    if (b->n_items > 0) {
+    if (b->n_chunks > 0) {
         BatchParams bp;
-        bp.streams = b->d_streams;
-        bp.items = b->d_items;
-        bp.n_items = b->n_items;
+        bp.chunks = b->d_chunks;
+        bp.n_full = b->n_full;
+        bp.n_chunks = b->n_chunks;
         bp.tables = b->d_tables;
-        bp.counter = b->d_counter;
-        hipError_t e = batch_table().fn[b->sidx](bp, st, b->grid);
+        hipError_t e = batch_table().fn[b->sidx](bp, st, b->grid, b->tail_grid);
         if (e != hipSuccess) return hip_fail(e);
     }
     for (int32_t idx : b->fallback) {
@@ -281,7 +300,7 @@ DPD_EXPORT dpd_status dpd_batch_apply_each(dpd_batch *b, void *stream)
 DPD_EXPORT dpd_status dpd_batch_info(const dpd_batch *b, int64_t *n_tiles, int32_t *n_blocks)
 {
     if (b == nullptr || n_tiles == nullptr || n_blocks == nullptr) return DPD_EINVAL;
-    *n_tiles = b->n_items;
+    *n_tiles = b->n_chunks;
     *n_blocks = b->grid;
     return DPD_OK;
 }

@@ -134,8 +134,13 @@ __global__ void __launch_bounds__(kBlock) bwd_dc_generic(BwdParams p, int NI, in
     }
 }
 
-// FP64 sum of the per-block partials in block order, then the chain rule from
-// the 2x2 matrices back to the stacked coefficients (section 2.2 layout):
+// Coefficient-gradient finalisation: block q sums, in FP64, the partials of
+// the four entries of table matrix q = k*NI + j (block L*NI: the two entries
+// of c) over all nblk producer blocks -- thread t takes producers t, t + 256,
+// ... in order, then a fixed butterfly in each wave and the four waves in
+// order, so the result is bitwise reproducible -- and applies the chain rule
+// through M = [[hr+gr, gi-hi], [hi+gi, hr-gr]] to the main and conjugate
+// coefficients of order 2j+1, tap k (section 2.2 layout):
 //   u1 = dE/dm00, u4 = dE/dm01, u3 = dE/dm10, u2 = dE/dm11
 //   grad h    = (u1 + u2) + j (u3 - u4)
 //   grad hbar = (u1 - u2) + j (u3 + u4)
@@ -143,31 +148,46 @@ __global__ void __launch_bounds__(kBlock) bwd_dc_generic(BwdParams p, int NI, in
 __global__ void __launch_bounds__(kBlock) bwd_finalize(const float *__restrict__ partials, int nblk,
                                                        CoefMap map, float2 *__restrict__ gcoef)
 {
-    __shared__ double sum[4 * kMaxL * kMaxNI + 2];
+    __shared__ double red[kBlock / 64][4];
     const int L = map.L, NI = map.NI, E = 4 * L * NI + 2;
-    for (int e = threadIdx.x; e < E; e += kBlock) {
-        double t = 0.0;
-        for (int b = 0; b < nblk; ++b) t += (double)partials[(int64_t)b * E + e];
-        sum[e] = t;
+    const int q = blockIdx.x;
+    const bool dc = q == L * NI;
+    const int base = 4 * q;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+        const float *pp = partials + (int64_t)b * E + base;
+        a[0] += (double)pp[0];
+        a[1] += (double)pp[1];
+        if (!dc) {
+            a[2] += (double)pp[2];
+            a[3] += (double)pp[3];
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) a[e] += __shfl_xor(a[e], off, 64);
+        if (lane == 0) red[wv][e] = a[e];
     }
     __syncthreads();
-    const int K = (map.n_main + map.n_conj) * L + 1;
-    for (int t = threadIdx.x; t < K; t += kBlock) {
-        if (t == K - 1) {
-            gcoef[t] = make_float2((float)sum[E - 2], (float)sum[E - 1]);
-            continue;
-        }
-        const int br = t / L, k = t - br * L;
-        const bool conj = br >= map.n_main;
-        const int bi = conj ? br - map.n_main : br;
-        int j = 0;
-        for (int q = 0; q < kMaxNI; ++q)
-            if ((conj ? map.conj_idx[q] : map.main_idx[q]) == bi) j = q;
-        const double *u = &sum[4 * (k * NI + j)];
-        const double u1 = u[0], u4 = u[1], u3 = u[2], u2 = u[3];
-        gcoef[t] = conj ? make_float2((float)(u1 - u2), (float)(u3 + u4))
-                        : make_float2((float)(u1 + u2), (float)(u3 - u4));
+    if (threadIdx.x != 0) return;
+    double u[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        u[e] = red[0][e];
+        for (int w = 1; w < kBlock / 64; ++w) u[e] += red[w][e];
     }
+    if (dc) {
+        gcoef[(map.n_main + map.n_conj) * L] = make_float2((float)u[0], (float)u[1]);
+        return;
+    }
+    const int k = q / NI, j = q - k * NI;
+    const double u1 = u[0], u4 = u[1], u3 = u[2], u2 = u[3];
+    if (map.main_idx[j] >= 0)
+        gcoef[map.main_idx[j] * L + k] = make_float2((float)(u1 + u2), (float)(u3 - u4));
+    if (map.conj_idx[j] >= 0)
+        gcoef[(map.n_main + map.conj_idx[j]) * L + k] = make_float2((float)(u1 - u2), (float)(u3 + u4));
 }
 
 static bool spec_ok(const CoefMap &m) { return m.NI <= kSpecNI && m.L <= kSpecL; }
@@ -238,8 +258,8 @@ DPD_EXPORT dpd_status dpd_backward(dpd_plan *plan, void *stream, const void *coe
         if (aligned && spec_ok(map)) {
             const int want = want_dx && want_dc ? 2 : (want_dc ? 1 : 0);
             const int64_t C = 64 * kBwdS;
-            p.tpr = (n + C - 1) / C;
-            const int64_t chunks = rows * p.tpr;
+            p.tpr = n / C;
+            const int64_t chunks = rows * ((n + C - 1) / C);
             const int64_t cap = (int64_t)num_cus() * std::min(8, bwd_occupancy(map.NI, map.L, want));
             const int64_t grid = std::max<int64_t>(1, std::min(cap, (chunks + 3) / 4));
             hipError_t e = bwd_table().fn[map.NI - 1][map.L - 1][want](p, st, (int)grid);
@@ -266,8 +286,8 @@ DPD_EXPORT dpd_status dpd_backward(dpd_plan *plan, void *stream, const void *coe
         }
     }
     if (want_dc) {
-        hipLaunchKernelGGL(bwd_finalize, dim3(1), dim3(kBlock), 0, st, (const float *)ws, nblk, map,
-                           (float2 *)grad_coeffs);
+        hipLaunchKernelGGL(bwd_finalize, dim3((uint32_t)(map.L * map.NI + 1)), dim3(kBlock), 0, st,
+                           (const float *)ws, nblk, map, (float2 *)grad_coeffs);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e);
     }

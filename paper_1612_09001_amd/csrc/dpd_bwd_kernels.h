@@ -30,7 +30,7 @@ struct BwdParams {
     float2 *gx;           // nullptr: no input gradient
     float *partials;      // [gridDim.x][E] (E = 4*L*NI + 2), nullptr: no coeff gradient
     int64_t n, ld, rows;
-    int64_t tpr;          // chunks per row (ceil)
+    int64_t tpr;          // full chunks per row (n / (64*S)); the ragged end is extra
     const float *M;       // precombined table
 };
 
@@ -60,10 +60,23 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
-// Persistent grid; wave g processes chunks g, g + nw, ... of C = 64*S samples
-// (rows flattened, each row zero-padded beyond n).  Per chunk the wave stages
-// G (the chunk plus the L-1 samples after it) in a padded wave-private LDS
-// buffer; each lane owns S consecutive samples m and reads G_{m..m+S+L-2}.
+template <bool B>
+struct BwdTag {
+    static constexpr bool value = B;
+};
+
+// Persistent grid over the full chunks (C = 64*S samples) of all rows, wave g
+// taking chunks g, g + nw, ... (rows flattened), then the ragged row ends.
+// Per chunk the wave stages G (the chunk plus the L-1 samples after it; zero
+// past the row end) and x (the chunk) in padded wave-private LDS buffers,
+// with nontemporal 1 KiB-contiguous loads issued one chunk ahead: a chunk's
+// registers are staged right after the previous chunk's stores, and the next
+// chunk's loads go out into the same registers before the staged chunk is
+// filtered, so the compiler's counter waits never cover the prefetch.  Each
+// lane owns S consecutive samples m and reads G_{m..m+S+L-2}.  One pass over
+// the power levels j (ascending) produces both gradients: U_j by taps for dx
+// (P = sum s^j U_j and Q = sum j s^(j-1) v.U_j accumulated with explicit
+// powers), and G (x) s^j v into the per-lane coefficient accumulators.
 template <int NI, int L, bool DX, bool DC>
 __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
 {
@@ -72,85 +85,91 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
     constexpr int W = S + L - 1;
     constexpr int NV = S / 2;
     constexpr int WAVES = kBlock / 64;
-    constexpr int E = 4 * L * NI + 2;
+    constexpr int NM = 4 * L * NI;                              // matrix floats (c has no gradient path here)
+    constexpr int E = NM + 2;
     constexpr int HS = L - 1;                                   // right halo
-    constexpr int SLOTS = 64 * (S + 1) + HS + (HS + S - 1) / S + 1;
-    __shared__ __align__(16) float2 gs[WAVES][SLOTS];
+    constexpr int GSLOTS = C + HS + (C + HS) / S + 1;
+    constexpr int XSLOTS = C + C / S;
+    __shared__ __align__(16) float2 gs[WAVES][GSLOTS];
+    __shared__ __align__(16) float2 xsh[WAVES][XSLOTS];
+    __shared__ __align__(16) float mt[NM];
     __shared__ float red[DC ? WAVES * E : 1];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const cfloat *M = as_const(p.M);
+    for (int e = tid; e < NM; e += kBlock) mt[e] = p.M[e];
+    __syncthreads();
     float2 *G = gs[wv];
-    // slot of chunk-relative sample d (0 <= d < C + HS): one pad after every S
+    float2 *X = xsh[wv];
+    // slot of chunk-relative sample d: one pad after every S
     auto slot = [](int d) { return d + d / S; };
+    const int hl = HS > 0 ? (lane < HS ? lane : HS - 1) : 0;
 
     float acc[DC ? E : 1];
 #pragma unroll
     for (int e = 0; e < (DC ? E : 1); ++e) acc[e] = 0.f;
 
-    const int64_t total = p.rows * p.tpr;
-    const int64_t nw = (int64_t)gridDim.x * WAVES;
-    const int64_t gw = (int64_t)blockIdx.x * WAVES + wv;
-    const int hl = HS > 0 ? (lane < HS ? lane : HS - 1) : 0;
-
-    for (int64_t c = gw; c < total; c += nw) {
-        const int64_t row = c / p.tpr;
-        const int64_t t0 = (c - row * p.tpr) * C;
-        const float2 *xr = p.x + row * p.ld;
-        const float2 *gr = p.gz + row * p.ld;
-        const bool full = t0 + C <= p.n;
-        // G chunk (load order: lane l, part i -> samples 2(l + 64 i)) and halo
-        float4 gv[NV];
-        if (full) {
-            const float4 *g4 = reinterpret_cast<const float4 *>(gr + t0);
+    struct Regs {
+        float4 g[NV];
+        float4 x[NV];
+        float2 gh;   // raw G_{t0 + C + hl} (replaced by zero past the row end at staging)
+    };
+    // full chunk at (row, t0): every load unconditional
+    auto load_full = [&](Regs &R, int64_t row, int64_t t0) {
+        const v4f *g4 = reinterpret_cast<const v4f *>(p.gz + row * p.ld + t0);
+        const v4f *x4 = reinterpret_cast<const v4f *>(p.x + row * p.ld + t0);
 #pragma unroll
-            for (int i = 0; i < NV; ++i) gv[i] = g4[lane + 64 * i];
-        } else {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                const int64_t m = t0 + 2 * (lane + 64 * i);
-                const float2 u = m < p.n ? gr[m] : make_float2(0.f, 0.f);
-                const float2 w = m + 1 < p.n ? gr[m + 1] : make_float2(0.f, 0.f);
-                gv[i] = make_float4(u.x, u.y, w.x, w.y);
-            }
+        for (int i = 0; i < NV; ++i) {
+            const v4f u = __builtin_nontemporal_load(g4 + lane + 64 * i);
+            R.g[i] = make_float4(u.x, u.y, u.z, u.w);
         }
-        float2 gh = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const v4f u = __builtin_nontemporal_load(x4 + lane + 64 * i);
+            R.x[i] = make_float4(u.x, u.y, u.z, u.w);
+        }
         if (HS > 0) {
             const int64_t m = t0 + C + hl;
-            const float2 t = gr[m < p.n ? m : p.n - 1];
-            gh = m < p.n ? t : make_float2(0.f, 0.f);
+            R.gh = p.gz[row * p.ld + (m < p.n ? m : p.n - 1)];
         }
-        // own samples of x (S consecutive per lane)
-        float xa[S], xb[S];
-        const int64_t m0 = t0 + (int64_t)lane * S;
-        if (full) {
-            const float4 *x4 = reinterpret_cast<const float4 *>(xr + m0);
+    };
+    // ragged row end: samples past n read as zero
+    auto load_part = [&](Regs &R, int64_t row, int64_t t0) {
+        const float2 *gr = p.gz + row * p.ld;
+        const float2 *xr = p.x + row * p.ld;
 #pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                const float4 v = x4[i];
-                xa[2 * i] = v.x;
-                xb[2 * i] = v.y;
-                xa[2 * i + 1] = v.z;
-                xb[2 * i + 1] = v.w;
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < S; ++i) {
-                const float2 v = m0 + i < p.n ? xr[m0 + i] : make_float2(0.f, 0.f);
-                xa[i] = v.x;
-                xb[i] = v.y;
-            }
+        for (int i = 0; i < NV; ++i) {
+            const int64_t m = t0 + 2 * (lane + 64 * i);
+            const float2 a = m < p.n ? gr[m] : make_float2(0.f, 0.f);
+            const float2 b = m + 1 < p.n ? gr[m + 1] : make_float2(0.f, 0.f);
+            R.g[i] = make_float4(a.x, a.y, b.x, b.y);
+            const float2 c = m < p.n ? xr[m] : make_float2(0.f, 0.f);
+            const float2 d = m + 1 < p.n ? xr[m + 1] : make_float2(0.f, 0.f);
+            R.x[i] = make_float4(c.x, c.y, d.x, d.y);
         }
-        wave_lds_order();
+        R.gh = make_float2(0.f, 0.f);
+    };
+    auto stage = [&](const Regs &R, int64_t t0) {
+        wave_lds_order();   // the previous chunk's LDS reads are done
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const int j = 2 * (lane + 64 * i);
-            G[slot(j)] = make_float2(gv[i].x, gv[i].y);
-            G[slot(j) + 1] = make_float2(gv[i].z, gv[i].w);
+            G[slot(j)] = make_float2(R.g[i].x, R.g[i].y);
+            G[slot(j) + 1] = make_float2(R.g[i].z, R.g[i].w);
+            X[slot(j)] = make_float2(R.x[i].x, R.x[i].y);
+            X[slot(j) + 1] = make_float2(R.x[i].z, R.x[i].w);
         }
-        if (HS > 0 && lane < HS) G[slot(C + lane)] = gh;
+        if (HS > 0 && lane < HS) G[slot(C + lane)] = t0 + C + lane < p.n ? R.gh : make_float2(0.f, 0.f);
         wave_lds_order();
+    };
+    // gradients of a staged chunk; FULL: every sample of it is inside the row
+    auto compute = [&](int64_t row, int64_t t0, auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        // An opaque zero keeps the table reads inside the loop (hoisted, the
+        // whole table would occupy registers next to the accumulators).
+        int z = 0;
+        asm volatile("" : "+v"(z));
+        const float4 *M4 = reinterpret_cast<const float4 *>(mt + z);
         float ga[W], gb[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) {
@@ -158,61 +177,98 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
             ga[w] = g.x;
             gb[w] = g.y;
         }
-
-        float dxa[S], dxb[S];
+        float va[S], vb[S], sq[S];
 #pragma unroll
         for (int i = 0; i < S; ++i) {
-            const float a = xa[i], b = xb[i];
-            const float s = __builtin_fmaf(a, a, b * b);
-            if constexpr (DC) {
-                // coefficient gradient: G_{m+k} (x) s^j v
-                float pa = a, pb = b;
+            const float2 v = X[slot(lane * S + i)];
+            va[i] = v.x;
+            vb[i] = v.y;
+            sq[i] = __builtin_fmaf(v.x, v.x, v.y * v.y);
+        }
+        float Pa[S], Pb[S], Q[S], pw[S], pwl[S];
 #pragma unroll
-                for (int j = 0; j < NI; ++j) {
+        for (int i = 0; i < S; ++i) {
+            Pa[i] = Pb[i] = Q[i] = 0.f;
+            pw[i] = 1.f;     // s^j
+            pwl[i] = 0.f;    // j s^(j-1)
+        }
 #pragma unroll
-                    for (int k = 0; k < L; ++k) {
-                        float *u = &acc[4 * (k * NI + j)];
-                        u[0] = __builtin_fmaf(ga[i + k], pa, u[0]);
-                        u[1] = __builtin_fmaf(ga[i + k], pb, u[1]);
-                        u[2] = __builtin_fmaf(gb[i + k], pa, u[2]);
-                        u[3] = __builtin_fmaf(gb[i + k], pb, u[3]);
+        for (int j = 0; j < NI; ++j) {
+            float Ua[S], Ub[S], ba[S], bb[S];
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                Ua[i] = Ub[i] = 0.f;
+                ba[i] = pw[i] * va[i];
+                bb[i] = pw[i] * vb[i];
+            }
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                const float4 m = M4[k * NI + j];   // [[m.x, m.y], [m.z, m.w]]
+#pragma unroll
+                for (int i = 0; i < S; ++i) {
+                    const float a = ga[i + k], b = gb[i + k];
+                    if constexpr (DX) {
+                        Ua[i] = __builtin_fmaf(m.x, a, Ua[i]);
+                        Ua[i] = __builtin_fmaf(m.z, b, Ua[i]);
+                        Ub[i] = __builtin_fmaf(m.y, a, Ub[i]);
+                        Ub[i] = __builtin_fmaf(m.w, b, Ub[i]);
                     }
-                    pa *= s;
-                    pb *= s;
+                    if constexpr (DC) {
+                        float *u = &acc[4 * (k * NI + j)];
+                        u[0] = __builtin_fmaf(a, ba[i], u[0]);
+                        u[1] = __builtin_fmaf(a, bb[i], u[1]);
+                        u[2] = __builtin_fmaf(b, ba[i], u[2]);
+                        u[3] = __builtin_fmaf(b, bb[i], u[3]);
+                    }
                 }
+            }
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                if constexpr (DX) {
+                    Pa[i] = __builtin_fmaf(pw[i], Ua[i], Pa[i]);
+                    Pb[i] = __builtin_fmaf(pw[i], Ub[i], Pb[i]);
+                    if (j > 0) {
+                        const float d = __builtin_fmaf(va[i], Ua[i], vb[i] * Ub[i]);
+                        Q[i] = __builtin_fmaf(pwl[i], d, Q[i]);
+                    }
+                    pwl[i] = (float)(j + 1) * pw[i];
+                }
+                pw[i] *= sq[i];
+            }
+            // One power level at a time: the empty asm statements consume this
+            // level's results, so the instruction selector cannot sink its
+            // multiply-adds past the barrier (it did, which kept every
+            // level's table entries live at once); only this level's L
+            // table entries are in registers.
+            if constexpr (DC) {
+#pragma unroll
+                for (int k = 0; k < L; ++k)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) asm volatile("" ::"v"(acc[4 * (k * NI + j) + q]));
+            }
+            if constexpr (DX) {
+#pragma unroll
+                for (int i = 0; i < S; ++i) asm volatile("" ::"v"(Pa[i]), "v"(Pb[i]), "v"(Q[i]));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if constexpr (DC) {
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
                 acc[E - 2] += ga[i];
                 acc[E - 1] += gb[i];
             }
-            if constexpr (DX) {
-                // U_j by taps, then Horner in s for P = sum s^j U_j and
-                // Q = sum j s^(j-1) (v . U_j)
-                float Pa = 0.f, Pb = 0.f, Q = 0.f;
-#pragma unroll
-                for (int j = NI - 1; j >= 0; --j) {
-                    float ua = 0.f, ub = 0.f;
-#pragma unroll
-                    for (int k = 0; k < L; ++k) {
-                        const cfloat *Mk = M + 4 * (k * NI + j);
-                        ua = __builtin_fmaf(Mk[0], ga[i + k], ua);
-                        ua = __builtin_fmaf(Mk[2], gb[i + k], ua);
-                        ub = __builtin_fmaf(Mk[1], ga[i + k], ub);
-                        ub = __builtin_fmaf(Mk[3], gb[i + k], ub);
-                    }
-                    Pa = __builtin_fmaf(Pa, s, ua);
-                    Pb = __builtin_fmaf(Pb, s, ub);
-                    if (j > 0) {
-                        const float d = __builtin_fmaf(a, ua, b * ub);
-                        Q = __builtin_fmaf(Q, s, (float)j * d);
-                    }
-                }
-                const float q2 = 2.f * Q;
-                dxa[i] = __builtin_fmaf(q2, a, Pa);
-                dxb[i] = __builtin_fmaf(q2, b, Pb);
-            }
         }
         if constexpr (DX) {
+            float dxa[S], dxb[S];
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                const float q2 = 2.f * Q[i];
+                dxa[i] = __builtin_fmaf(q2, va[i], Pa[i]);
+                dxb[i] = __builtin_fmaf(q2, vb[i], Pb[i]);
+            }
             float2 *gxr = p.gx + row * p.ld;
-            if (full) {
+            if constexpr (FULL) {
                 // back through LDS so every store instruction writes 1 KiB
                 wave_lds_order();
 #pragma unroll
@@ -227,10 +283,47 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
                     __builtin_nontemporal_store(v, o4 + lane + 64 * i);
                 }
             } else {
+                const int64_t m0 = t0 + (int64_t)lane * S;
 #pragma unroll
                 for (int i = 0; i < S; ++i)
                     if (m0 + i < p.n) gxr[m0 + i] = make_float2(dxa[i], dxb[i]);
             }
+        }
+    };
+
+    const int64_t tpr = p.tpr;                   // full chunks per row
+    const int64_t total = p.rows * tpr;
+    const int64_t nw = (int64_t)gridDim.x * WAVES;
+    const int64_t gw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * WAVES + wv;
+    if (gw < total) {
+        const int64_t left = (total - 1 - gw) / nw + 1;
+        // (row, chunk in row) advanced by nw chunks per step without a division
+        const int64_t dq = nw / tpr, dr = nw - dq * tpr;
+        int64_t row = gw / tpr, tix = gw - row * tpr;
+        Regs R;
+        load_full(R, row, tix * C);
+        stage(R, tix * C);
+        for (int64_t i = 0; i + 1 < left; ++i) {
+            const int64_t crow = row, ct0 = tix * C;
+            row += dq;
+            tix += dr;
+            if (tix >= tpr) {
+                tix -= tpr;
+                ++row;
+            }
+            load_full(R, row, tix * C);
+            compute(crow, ct0, BwdTag<true>{});
+            stage(R, tix * C);
+        }
+        compute(row, tix * C, BwdTag<true>{});
+    }
+    // ragged row ends continue the round-robin order (chunk c to wave c mod nw)
+    if (p.n > tpr * C) {
+        for (int64_t r = (gw + nw - total % nw) % nw; r < p.rows; r += nw) {
+            Regs R;
+            load_part(R, r, tpr * C);
+            stage(R, tpr * C);
+            compute(r, tpr * C, BwdTag<false>{});
         }
     }
 

@@ -32,6 +32,15 @@ __device__ __forceinline__ const cfloat *as_const(const float *p)
     return (const cfloat *)p;
 }
 
+// Global-address-space views, for pointers the compiler cannot trace back to
+// a kernel argument (so loads and stores become global_*, not flat_*, and
+// only count against the vector-memory counter).
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef const v2f __attribute__((address_space(1))) gcv2f;
+typedef const v4f __attribute__((address_space(1))) gcv4f;
+typedef v2f __attribute__((address_space(1))) gv2f;
+typedef v4f __attribute__((address_space(1))) gv4f;
+
 // Consecutive tiles share a halo; keep neighbours on one XCD (one L2) by
 // mapping dispatch order (round-robin over the 8 XCDs) to contiguous ranges.
 __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G)

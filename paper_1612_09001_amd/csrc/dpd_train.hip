@@ -5,7 +5,7 @@
 //   Adam  (Kingma & Ba) on real parameters; complex parameters are their
 //         interleaved real and imaginary parts.
 // The loss reduction is deterministic: fixed grid, fixed in-block tree, one
-// partial per block, FP64 sum of the partials in block order.
+// partial per block, then a fixed-order FP64 sum of the partials.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,13 +45,23 @@ __global__ void __launch_bounds__(kBlock) loss_kernel(const float2 *__restrict__
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
+// FP64 sum of the block partials: thread t takes partials t, t + 256, ... in
+// order, then a fixed butterfly in each wave and the four waves in order
+// (bitwise reproducible for a given partial count).
 __global__ void __launch_bounds__(kBlock) loss_finalize(const float *__restrict__ partials, int nblk, double inv_n,
                                                         float *__restrict__ loss)
 {
+    __shared__ double red[kBlock / 64];
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) t += (double)partials[b];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int b = 0; b < nblk; ++b) t += (double)partials[b];
-        *loss = (float)(t * inv_n);
+        double u = red[0];
+        for (int w = 1; w < kBlock / 64; ++w) u += red[w];
+        *loss = (float)(u * inv_n);
     }
 }
 

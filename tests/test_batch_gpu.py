@@ -27,8 +27,10 @@ def mods(torch):
 
 
 SMALL_SPECS = [  # (n, P_max, L) -- ragged lengths, every class shape, fallbacks
-    (0, 5, 3), (1, 5, 2), (7, 7, 8), (4095, 9, 8), (4096, 5, 1), (4097, 7, 4), (20000, 3, 6),
+    (0, 5, 3), (1, 5, 2), (7, 7, 8), (8191, 9, 8), (8192, 5, 1), (8193, 7, 4), (20000, 3, 6),
     (12345, 1, 5), (70001, 9, 2), (3, 11, 3), (5000, 5, 11), (65536, 7, 4), (1023, 9, 5),
+    (16384, 9, 8), (16900, 7, 7), (24577, 3, 3), (511, 9, 8), (512, 7, 7), (513, 5, 3), (129, 3, 2),
+    (256, 9, 1), (127, 7, 6),
 ]
 
 
@@ -45,8 +47,11 @@ def _check_streams(wl, z, orc, count=None):
             ref = orc.forward(x, orders, orders, L, h)
             assert_parity(got, ref, "stream %d" % s)
         else:
-            edges = (np.arange(1, n // 4096 + 1) * 4096)[:, None] + np.arange(-9, 9)[None, :]
-            idx = np.unique(np.concatenate([np.arange(0, 20), np.arange(n - 20, n), edges.reshape(-1)]))
+            # chunk (512-sample) edges: every 16th, and all in the first 32768 samples
+            edges = (np.arange(1, n // 8192 + 1) * 8192)[:, None] + np.arange(-9, 9)[None, :]
+            chunks = (np.arange(1, min(n, 32768) // 512 + 1) * 512)[:, None] + np.arange(-2, 2)[None, :]
+            idx = np.unique(np.concatenate([np.arange(0, 20), np.arange(n - 20, n), edges.reshape(-1),
+                                            chunks.reshape(-1)]))
             idx = idx[(idx >= 0) & (idx < n)]
             idx = np.unique(np.concatenate([idx, rng.integers(0, n, count)]))
             assert_parity(got[idx], orc.forward_at(x, orders, orders, L, h, idx), "stream %d" % s)
@@ -77,7 +82,7 @@ def _written(wl, z):
     return np.concatenate([z[o:o + n] for o, (n, _, _) in zip(wl.offsets, wl.specs)])
 
 
-def test_counter_resets_and_graph_replay(torch, mods):
+def test_repeat_and_graph_replay(torch, mods):
     dpd, batch = mods
     wl = batch.BatchWorkload(SMALL_SPECS, config_id=71)
     b = batch.Batch(wl.streams())
@@ -126,7 +131,7 @@ def test_config4_full_sampled(torch, mods, orc):
     wl = batch.BatchWorkload(signals.batch_specs(), config_id=4)
     b = batch.Batch(wl.streams())
     ntiles, nblocks = b.info()
-    assert ntiles == sum((n + 4095) // 4096 for n, _, _ in wl.specs)
+    assert ntiles == sum((n + 511) // 512 for n, _, _ in wl.specs)   # chunks of 64 * 8 samples
     b.apply()
     z = wl.z.cpu().numpy()
     _check_streams(wl, z, orc, count=2000)
