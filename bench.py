@@ -265,14 +265,26 @@ def main():
     ap.add_argument("--tune", default="", help="S,LDS[,GRID_MULT] override, e.g. 8,1,16")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the same bytes (counter calibration)")
+    ap.add_argument("--only-leg", default="",
+                    help="run only these secondary workloads (comma-separated: config3, config4, backward, "
+                         "config5) and print their results, e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(DESIGN.md describes how the path would shard)" % args.gpus, file=sys.stderr)
+        print("bench.py: measures one GPU only; --gpus %d is not supported (the forward map, the "
+              "batch and the training step shard without cross-GPU traffic in the hot path)" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_1612_09001_amd import dpd, signals
+    legs = {"config3": leg_config3, "config4": leg_config4, "backward": leg_backward, "config5": leg_config5}
+    if args.only_leg:
+        for name in args.only_leg.split(","):
+            if name not in legs:
+                print("bench.py: unknown workload %r (known: %s)" % (name, ", ".join(legs)), file=sys.stderr)
+                sys.exit(2)
+            print(json.dumps({name: legs[name](torch, dpd, signals)}), flush=True)
+        return
 
     n = 1 << args.log2n
     mo = co = [1, 3, 5, 7]
@@ -336,8 +348,7 @@ def main():
     if not args.main_only:
         del xs
         sec = {}
-        for name, fn in (("config3", leg_config3), ("config4", leg_config4),
-                         ("backward", leg_backward), ("config5", leg_config5)):
+        for name, fn in legs.items():
             try:
                 sec[name] = fn(torch, dpd, signals)
             except Exception as e:  # a failing secondary leg must not hide the headline

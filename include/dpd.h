@@ -61,7 +61,7 @@ typedef struct dpd_batch dpd_batch;
  *   stage_lds: 1 = the tile and its (L-1)-sample halo are staged through LDS
  *              with coalesced 16-byte loads, 0 = each thread loads its own
  *              window (halo re-reads hit the cache)
- *   block: threads per block (fixed at 256 in this build)
+ *   block: threads per block (must be 256; other values are rejected)
  *   grid_mult: persistent batched kernel only -- resident blocks per CU */
 typedef struct dpd_tune {
     int32_t samples_per_thread;

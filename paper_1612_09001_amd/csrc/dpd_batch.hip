@@ -21,7 +21,8 @@ struct dpd_batch {
     std::vector<int32_t> tab;
     std::vector<int32_t> fallback;       // streams run by separate launches
     dpd::BatchChunk *d_chunks = nullptr;  // full chunks, ragged chunks, idle entry
-    dpd::BatchPrep *d_prep = nullptr;
+    dpd::BatchPrepJob *d_jobs = nullptr;
+    int32_t n_jobs = 0;
     float *d_tables = nullptr;
     float2 *d_idle = nullptr;              // samples the idle entry points at
     int64_t n_full = 0;
@@ -36,28 +37,21 @@ namespace dpd {
 
 int num_cus();
 
-// One block per stream: precombine its coefficients into the batch table.
-__global__ void __launch_bounds__(128) batch_prep_kernel(const BatchPrep *__restrict__ prep,
-                                                         float *__restrict__ tables)
+// Precombine every stream's coefficients into its table: one thread per
+// table entry (a flat job list built at create), one dependent load.
+__global__ void __launch_bounds__(kBlock) batch_prep_kernel(const BatchPrepJob *__restrict__ jobs, int32_t n_jobs,
+                                                            float *__restrict__ tables)
 {
-    const BatchPrep bp = prep[blockIdx.x];
-    const int L = bp.map.L, NI = bp.map.NI, t = threadIdx.x;
-    float *M = tables + bp.tab;
-    if (t < L * NI) {
-        const int k = t / NI, j = t - k * NI;
-        float2 h = make_float2(0.f, 0.f), g = make_float2(0.f, 0.f);
-        if (bp.map.main_idx[j] >= 0) h = bp.raw[bp.map.main_idx[j] * L + k];
-        if (bp.map.conj_idx[j] >= 0) g = bp.raw[(bp.map.n_main + bp.map.conj_idx[j]) * L + k];
-        M[4 * t + 0] = h.x + g.x;
-        M[4 * t + 1] = g.y - h.y;
-        M[4 * t + 2] = h.y + g.y;
-        M[4 * t + 3] = h.x - g.x;
-    }
-    if (t == 0) {
-        const int K = (bp.map.n_main + bp.map.n_conj) * L + 1;
-        const float2 c = bp.raw[K - 1];
-        M[4 * L * NI] = c.x;
-        M[4 * L * NI + 1] = c.y;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_jobs) return;
+    const BatchPrepJob jb = jobs[i];
+    const float2 h = jb.h != nullptr ? *jb.h : make_float2(0.f, 0.f);
+    const float2 g = jb.g != nullptr ? *jb.g : make_float2(0.f, 0.f);
+    if (jb.dc) {
+        tables[jb.out] = h.x;
+        tables[jb.out + 1] = h.y;
+    } else {
+        *reinterpret_cast<float4 *>(tables + jb.out) = make_float4(h.x + g.x, g.y - h.y, h.y + g.y, h.x - g.x);
     }
 }
 
@@ -94,7 +88,7 @@ static int batch_occupancy(int sidx)
 static void free_batch(dpd_batch *b)
 {
     if (b->d_chunks) (void)hipFree(b->d_chunks);
-    if (b->d_prep) (void)hipFree(b->d_prep);
+    if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->d_tables) (void)hipFree(b->d_tables);
     if (b->d_idle) (void)hipFree(b->d_idle);
     delete b;
@@ -113,8 +107,9 @@ static hipError_t upload(T **dst, const std::vector<T> &v)
 static dpd_status batch_prep(dpd_batch *b, hipStream_t st)
 {
     if (b->n_streams == 0) return DPD_OK;
-    hipLaunchKernelGGL(batch_prep_kernel, dim3((uint32_t)b->n_streams), dim3(128), 0, st, b->d_prep,
-                       b->d_tables);
+    if (b->n_jobs == 0) return DPD_OK;
+    hipLaunchKernelGGL(batch_prep_kernel, dim3((uint32_t)((b->n_jobs + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       b->d_jobs, b->n_jobs, b->d_tables);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? DPD_OK : hip_fail(e);
 }
@@ -147,7 +142,7 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
     b->sidx = t.samples_per_thread == 2 ? 0 : (t.samples_per_thread == 4 ? 1 : 2);
     b->n_streams = n_streams;
     b->desc.assign(desc, desc + n_streams);
-    std::vector<BatchPrep> prep(n_streams);
+    std::vector<BatchPrepJob> jobs;
     std::vector<int32_t> order;   // streams in the persistent kernel
     int64_t tab_total = 0;
     for (int32_t s = 0; s < n_streams; ++s) {
@@ -172,9 +167,27 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
         }
         b->maps.push_back(map);
         b->tab.push_back((int32_t)tab_total);
-        prep[s].raw = (const float2 *)d.coeffs_dev;
-        prep[s].map = map;
-        prep[s].tab = (int32_t)tab_total;
+        {
+            // table entries of this stream: matrix (k, j) at 4 (k NI + j), then c
+            const float2 *raw = (const float2 *)d.coeffs_dev;
+            for (int k = 0; k < map.L; ++k)
+                for (int j = 0; j < map.NI; ++j) {
+                    BatchPrepJob jb;
+                    jb.h = map.main_idx[j] >= 0 ? raw + map.main_idx[j] * map.L + k : nullptr;
+                    jb.g = map.conj_idx[j] >= 0 ? raw + (map.n_main + map.conj_idx[j]) * map.L + k : nullptr;
+                    jb.out = (int32_t)(tab_total + 4 * (k * map.NI + j));
+                    jb.dc = 0;
+                    jb.pad_ = 0;
+                    jobs.push_back(jb);
+                }
+            BatchPrepJob jc;
+            jc.h = raw + (map.n_main + map.n_conj) * map.L;
+            jc.g = nullptr;
+            jc.out = (int32_t)(tab_total + 4 * map.L * map.NI);
+            jc.dc = 1;
+            jc.pad_ = 0;
+            jobs.push_back(jc);
+        }
         tab_total += (table_floats(map.L, map.NI) + 3) & ~3;
         const bool aligned = (uintptr_t)d.in % 16 == 0 && (uintptr_t)d.out % 16 == 0;
         const bool in_kernel = aligned && map.NI <= kBatchMaxNI && map.L <= kBatchMaxL;
@@ -231,6 +244,10 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
     for (int32_t s : order)
         if (desc[s].n % C != 0) push(s, desc[s].n - desc[s].n % C, desc[s].n % C);
     b->n_chunks = (int64_t)chunks.size();
+    const int64_t cap = (int64_t)num_cus() * std::min(t.grid_mult, batch_occupancy(b->sidx));
+    const int64_t waves = kBlock / 64;
+    b->grid = (int)std::min<int64_t>(cap, (b->n_full + waves - 1) / waves);
+    b->tail_grid = (int)std::min<int64_t>(cap, (b->n_chunks - b->n_full + waves - 1) / waves);
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_idle, (size_t)C * sizeof(float2));
     if (e == hipSuccess) e = hipMemset(b->d_idle, 0, (size_t)C * sizeof(float2));
@@ -245,7 +262,8 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
         chunks.push_back(idle);
         e = upload(&b->d_chunks, chunks);
     }
-    if (e == hipSuccess) e = upload(&b->d_prep, prep);
+    if (e == hipSuccess) e = upload(&b->d_jobs, jobs);
+    b->n_jobs = (int32_t)jobs.size();
     // + 4 floats: the idle entry reads table floats 0..3
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_tables, (size_t)(tab_total + 4) * sizeof(float));
     if (e == hipSuccess) e = hipMemset(b->d_tables, 0, (size_t)(tab_total + 4) * sizeof(float));
@@ -254,10 +272,6 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
         free_batch(b);
         return e == hipErrorOutOfMemory ? DPD_ENOMEM : hip_fail(e);
     }
-    const int64_t cap = (int64_t)num_cus() * std::min(t.grid_mult, batch_occupancy(b->sidx));
-    const int64_t waves = kBlock / 64;
-    b->grid = (int)std::min<int64_t>(cap, (b->n_full + waves - 1) / waves);
-    b->tail_grid = (int)std::min<int64_t>(cap, (b->n_chunks - b->n_full + waves - 1) / waves);
     *out = b;
     return DPD_OK;
 }

@@ -50,12 +50,17 @@ __host__ __device__ constexpr uint32_t batch_meta(int cls, int hist, int nc4)
     return (uint32_t)cls | ((uint32_t)hist << 8) | ((uint32_t)nc4 << 16);
 }
 
-struct BatchPrep {
-    const float2 *raw;
-    CoefMap map;
-    int32_t tab;
-    int32_t pad_;
+// One entry of a stream's precombined table, rebuilt from the stream's
+// coefficients at every apply: the 2x2 matrix of (order 2j+1, tap k) from the
+// main and conjugate coefficients (either may be absent), or the DC term.
+struct BatchPrepJob {
+    const float2 *h;   // main-branch coefficient, or the DC term; nullptr: absent
+    const float2 *g;   // conjugate-branch coefficient; nullptr: absent
+    int32_t out;       // float offset in the tables (4 floats, 16-byte aligned; 2 for the DC term)
+    int32_t dc;        // 1: DC term
+    int64_t pad_;
 };
+static_assert(sizeof(BatchPrepJob) == 32, "job layout");
 
 struct BatchParams {
     const BatchChunk *chunks;   // [0, n_full) full, [n_full, n_chunks) ragged, [n_chunks] idle
