@@ -36,6 +36,7 @@ METRIC = "DPD Msamples/s + % HBM roofline at NMSE≤-110 dB vs oracle; grad-step
 HBM_PEAK_GBS = 8000.0
 VALU_FP32_PEAK_TFLOPS = 157.3      # published (packed FP32); non-packed issue: 78.6
 VALU_FP32_NONPACKED_TFLOPS = 78.6
+MFMA_FP32_TFLOPS = 157.3           # dense FP32 matrix-core peak of MI355X
 BYTES_PER_SAMPLE = 16              # 8 B complex64 read + 8 B written
 ROTATE_BYTES = 2 << 30
 PMC_FILE = os.path.join(ROOT, "profiles", "dpd_fwd_n2p24_P7_L4_pmc.txt")
@@ -211,6 +212,59 @@ def leg_backward(torch, dpd, signals, steps=50):
             "valu_frac_nonpacked": round(flops * n / (kmean * 1e-3) / 1e12 / VALU_FP32_NONPACKED_TFLOPS, 4)}
 
 
+def leg_ls(torch, dpd, signals, reps=5):
+    """Least-squares estimation (section 2.2, Eq. 2) with the headline basis
+    (orders {1,3,5,7} both branches, L = 4, K = 33): the matrix-core normal
+    equations over 2^20 and 2^24 samples, the FP64 Cholesky solve, and the
+    indirect-learning loop on the synthetic PA (2^18 samples, RMS 0.2)."""
+    from paper_1612_09001_amd import autotune, ila
+
+    orders, L = [1, 3, 5, 7], 4
+    plan = dpd.Plan(orders, orders, L, signals.aph_coeffs(orders, orders, L, config_id=1))
+    K = plan.K
+    D = 2 * K + 2
+    Dp = (D + 15) // 16 * 16
+    nt = Dp // 16
+    useful = D * (D + 1)                     # upper triangle of the real Gram, flops per sample
+    issued = nt * (nt + 1) // 2 * 16 * 16 * 2
+    st = dpd.current_stream()
+    out = {"workload": "normal equations of the K=33 headline basis; Cholesky solve; indirect learning",
+           "K": K, "real_features": D, "useful_flops_per_sample": useful, "mfma_flops_per_sample": issued}
+    for lg in (20, 24):
+        n = 1 << lg
+        y = torch.from_numpy(signals.ofdm_16qam(n, config_id=1)).cuda()
+        t = torch.from_numpy(signals.ofdm_16qam(n, config_id=1, stream_id=2)).cuda()
+        A = torch.empty((K, K), dtype=torch.complex128, device="cuda")
+        b = torch.empty(K, dtype=torch.complex128, device="cuda")
+        wsb = dpd.dpd_ls_ws_size(plan.handle, 1, n)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        us = autotune.time_us(lambda: dpd.dpd_ls_normal(plan.handle, st, y.data_ptr(), t.data_ptr(), 1, n, n, 1.0,
+                                                        ws.data_ptr(), wsb, A.data_ptr(), b.data_ptr()),
+                              warmup=3, iters=reps)
+        out["normal_2^%d_us" % lg] = round(us, 1)
+        out["normal_2^%d_useful_tflops" % lg] = round(useful * n / (us * 1e-6) / 1e12, 2)
+        out["normal_2^%d_mfma_tflops" % lg] = round(issued * n / (us * 1e-6) / 1e12, 2)
+        out["normal_2^%d_mfma_frac" % lg] = round(issued * n / (us * 1e-6) / 1e12 / MFMA_FP32_TFLOPS, 4)
+        del y, t, ws
+    h, info = dpd.ls_solve(A, b, 1e-9)
+    out["solve_us"] = round(autotune.time_us(lambda: dpd.ls_solve(A, b, 1e-9), warmup=2, iters=reps), 1)
+    x = torch.from_numpy(signals.ofdm_16qam(1 << 18, config_id=5, rms=0.2)).cuda()
+    est = ila.ILA(x, orders, orders, L)
+    e = [est.nmse_db()]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    est.step()
+    torch.cuda.synchronize()
+    out["ila_iteration_ms_2^18"] = round((time.perf_counter() - t0) * 1e3, 3)
+    e.append(est.nmse_db())
+    for _ in range(2):
+        est.step()
+        e.append(est.nmse_db())
+    out["ila_nmse_db_iters_0_to_3"] = [round(v, 2) for v in e]
+    out["ila_solve_info"] = int(est.info.item())
+    return out
+
+
 def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
     """64 x 2^18 samples, DPD orders {1,3,5,7} both branches, L = 6, identity
     start, synthetic PA, loss mean|y/10 - x|^2, Adam lr 1e-3."""
@@ -267,7 +321,7 @@ def main():
                     help="also run one plain device copy of the same bytes (counter calibration)")
     ap.add_argument("--only-leg", default="",
                     help="run only these secondary workloads (comma-separated: config3, config4, backward, "
-                         "config5) and print their results, e.g. under a profiler")
+                         "config5, ls) and print their results, e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU only; --gpus %d is not supported (the forward map, the "
@@ -277,7 +331,8 @@ def main():
 
     import torch
     from paper_1612_09001_amd import dpd, signals
-    legs = {"config3": leg_config3, "config4": leg_config4, "backward": leg_backward, "config5": leg_config5}
+    legs = {"config3": leg_config3, "config4": leg_config4, "backward": leg_backward, "config5": leg_config5,
+            "ls": leg_ls}
     if args.only_leg:
         for name in args.only_leg.split(","):
             if name not in legs:

@@ -214,6 +214,48 @@ dpd_status dpd_loss_grad(void *stream, const void *y, const void *x, int64_t n, 
 dpd_status dpd_adam_step(void *stream, float *params, const float *grads, float *m, float *v,
                          int64_t count, int32_t step, float lr, float beta1, float beta2, float eps);
 
+/* ------------------------------------------------------- least squares --
+ * The paper's coefficient estimate (section 2.2, Eq. 2): with the plan's
+ * basis, row m of Psi is
+ *   [psi_p(y_{m-k}) for main orders p, taps k; conj(psi_q(y_{m-k})) for
+ *    conjugate orders q, taps k; 1]
+ * in the coefficient stacking of section 2.2 (K columns), samples before each
+ * row start taken as zero (the first n rows of the zero-filled element
+ * matrices of Eq. 2, per row).  The least-squares coefficients solve
+ *   (Psi^H Psi) h = Psi^H t.
+ * In the indirect-learning use, y is the PA output divided by its gain and t
+ * the PA input (the predistorter output); the fitted postdistorter is then
+ * copied into the predistorter.
+ *
+ * dpd_ls_ws_size -- workspace bytes for dpd_ls_normal on rows x n samples.
+ *   DPD_EUNSUPPORTED if 2K+2 > 192 (K > 95): the Gram kernel holds at most
+ *   12 x 12 tiles of 16 x 16.
+ *
+ * dpd_ls_normal -- A = Psi^H Psi (K x K complex128, row-major, Hermitian) and
+ *   b = Psi^H t (K complex128), summed over all rows, with Psi built from
+ *   y_scale * y (e.g. 1 / PA gain; finite).  y, t: device complex64,
+ *   rows x n at stride ld samples (ld >= n; ignored when rows == 1), 8-byte
+ *   aligned.  ws: device, >= dpd_ls_ws_size bytes, 256-byte aligned,
+ *   caller-owned scratch.  A, b: device, 8-byte aligned, overwritten.  FP32
+ *   products accumulated in FP32 over slabs of 4096 samples, the slabs summed
+ *   in FP64 in a fixed order: deterministic.  Allocates nothing, does not
+ *   synchronize; rows * n == 0 gives A = 0, b = 0. */
+dpd_status dpd_ls_ws_size(const dpd_plan *plan, int64_t rows, int64_t n, size_t *bytes);
+dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y, const void *t, int64_t rows,
+                         int64_t n, int64_t ld, float y_scale, void *ws, size_t ws_bytes, void *A, void *b);
+
+/* dpd_ls_solve -- solve (A + delta I) h = b by Cholesky in FP64 on the device,
+ *   delta = ridge * mean(Re diag A) (ridge >= 0; 0 for the plain normal
+ *   equations).  A: K x K complex128 Hermitian (only the lower triangle is
+ *   read), b: K complex128, both device, 16-byte aligned.  h: device, K
+ *   complex64 (the section 2.2 stacking, ready for dpd_set_coeffs_device).
+ *   info: device int32, set to 0 on success or j+1 when the pivot of column j
+ *   is not positive (h is then NaN); the host sees it after synchronizing.
+ *   ws: device, >= dpd_ls_solve_ws_size bytes, 16-byte aligned. */
+dpd_status dpd_ls_solve_ws_size(int32_t K, size_t *bytes);
+dpd_status dpd_ls_solve(void *stream, int32_t K, const void *A, const void *b, double ridge, void *ws,
+                        size_t ws_bytes, void *h, void *info);
+
 /* ------------------------------------------------------------------- misc -- */
 const char *dpd_status_string(dpd_status status);
 int dpd_last_hip_error(void);

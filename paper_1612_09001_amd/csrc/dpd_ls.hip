@@ -1,0 +1,496 @@
+// Least-squares coefficient estimation (section 2.2, Eq. 2) on the GPU: the
+// normal equations A = Psi^H Psi, b = Psi^H t of the APH basis, and their
+// Cholesky solve.  Used by the indirect-learning loop (postdistorter fitted
+// from PA output to PA input, then copied into the predistorter).
+//
+// Row m of Psi is [psi_p(y_{m-k}) ..., conj(psi_q(y_{m-k})) ..., 1] in the
+// section 2.2 stacking (K columns), with zero samples before each row start
+// (the first M rows of the zero-filled element matrices of Eq. (2)).
+//
+// Real formulation.  With the 2K+2 real features of a sample,
+//     f = [Re Psi_m (K), Im Psi_m (K), Re t_m, Im t_m],
+// the real Gram R = sum_m f f^T carries everything:
+//     Re A = R_rr + R_ii,      Im A = R_ri - R_ri^T,
+//     Re b = R_r,t_r + R_i,t_i,  Im b = R_r,t_i - R_i,t_r.
+// R is a dense contraction over samples, so it runs on the matrix cores:
+// v_mfma_f32_16x16x4f32 over 16x16 tiles of the upper triangle of R, the
+// features of 64 samples at a time staged in LDS.  Each block covers one slab
+// of 4096 samples and writes its FP32 tiles (at most 1024 products per
+// accumulator); the slabs are summed in FP64 in a fixed order (two levels),
+// so the result is deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <utility>
+
+#include "dpd.h"
+#include "dpd_plan.h"
+
+#define DPD_EXPORT extern "C" __attribute__((visibility("default")))
+
+namespace dpd {
+
+typedef float v4f_ls __attribute__((ext_vector_type(4)));
+
+constexpr int kLsTile = 64;         // samples staged per step
+constexpr int kLsSlab = 4096;       // samples per block / FP32 partial
+constexpr int kLsMaxDp = 192;       // padded real features (2K+2 rounded up to 16): K <= 95
+constexpr int kLsMaxNt = kLsMaxDp / 16;
+constexpr int kLsMaxPairs = kLsMaxNt * (kLsMaxNt + 1) / 2;
+constexpr int kLsWaves = kBlock / 64;
+constexpr int kLsPairsPerWave = (kLsMaxPairs + kLsWaves - 1) / kLsWaves;
+constexpr int kLsGroup = 64;        // slabs per first-level FP64 sum
+constexpr int kLsStride = kLsMaxDp + 4;   // LDS row stride (floats)
+
+struct LsParams {
+    const float2 *y;        // basis input, rows x ld
+    const float2 *t;        // target, same layout
+    int64_t n, ld;
+    int64_t slabs_per_row;
+    float y_scale;          // the basis is built from y_scale * y
+    float *partials;        // [slab][pair][256]
+    int K, D, Dp, nt, npairs;
+    int L, NI;
+    int16_t cm[kMaxNI];     // first column of the main-branch taps of level j, or -1
+    int16_t cc[kMaxNI];     // the same for the conjugate branch
+};
+
+// Tile pair q of the upper triangle, row-major over (I <= J).
+__device__ __forceinline__ void ls_pair(int q, int nt, int &I, int &J)
+{
+    I = 0;
+    while (q >= nt - I) {
+        q -= nt - I;
+        ++I;
+    }
+    J = I + q;
+}
+
+// MAXP: tile pairs per wave (ceil(npairs / 4); one instance per count, so
+// the matrix-core loop has no conditionals -- a guarded accumulation becomes a
+// branch whose merge copies every accumulator).  Surplus slots of the last
+// waves accumulate tile (0, 0) and are not written out.
+template <int MAXP>
+__global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
+{
+    __shared__ float X[kLsTile][kLsStride];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t slab = blockIdx.x;
+    const int64_t row = slab / p.slabs_per_row;
+    const int64_t s0 = (slab - row * p.slabs_per_row) * kLsSlab;
+    const float2 *yr = p.y + row * p.ld;
+    const float2 *tr = p.t + row * p.ld;
+    const int pad = p.Dp - p.D;
+    if (pad > 0)
+        for (int e = tid; e < kLsTile * pad; e += kBlock) X[e / pad][p.D + e % pad] = 0.f;
+
+    // this wave's tiles: pairs wv, wv + 4, ...
+    const int mine = (p.npairs - wv + kLsWaves - 1) / kLsWaves;
+    int pI[MAXP], pJ[MAXP];
+    v4f_ls acc[MAXP];
+#pragma unroll
+    for (int u = 0; u < MAXP; ++u) {
+        pI[u] = pJ[u] = 0;
+        if (u < mine) ls_pair(wv + kLsWaves * u, p.nt, pI[u], pJ[u]);
+        acc[u] = v4f_ls{0.f, 0.f, 0.f, 0.f};
+    }
+
+    const int s = tid & (kLsTile - 1);   // sample of the tile this thread builds
+    const int part = tid / kLsTile;      // taps part, part + 4, ...
+    const int64_t send = std::min<int64_t>(s0 + kLsSlab, p.n);
+    // The samples a thread needs for a tile (y_{m-k} for its taps, t_m) are
+    // loaded one tile ahead, during the previous tile's matrix-core phase.
+    constexpr int KT = kMaxL / kLsWaves;
+    float2 yv[KT];
+    float2 tv = make_float2(0.f, 0.f);
+    auto fetch = [&](int64_t m0) {
+        const int64_t m = m0 + s;
+#pragma unroll
+        for (int i = 0; i < KT; ++i) {
+            const int k = part + kLsWaves * i;
+            const int64_t mk = m - k;
+            yv[i] = (k < p.L && m < p.n && mk >= 0) ? yr[mk] : make_float2(0.f, 0.f);
+        }
+        tv = (part == 0 && m < p.n) ? tr[m] : make_float2(0.f, 0.f);
+    };
+    fetch(s0);
+    for (int64_t m0 = s0; m0 < send; m0 += kLsTile) {
+        __syncthreads();   // the previous tile's matrix-core reads are done
+        const int64_t m = m0 + s;
+        // an opaque zero keeps the feature addresses (up to 4 taps x 8 levels
+        // x 4 columns, all loop-invariant) from being hoisted into registers
+        int z = 0;
+        asm volatile("" : "+v"(z));
+        float *xs = X[s] + z;
+        if (m < p.n) {
+#pragma unroll
+            for (int i = 0; i < KT; ++i) {
+                const int k = part + kLsWaves * i;
+                if (k < p.L) {
+                    const float2 v = make_float2(p.y_scale * yv[i].x, p.y_scale * yv[i].y);
+                    const float s2 = __builtin_fmaf(v.x, v.x, v.y * v.y);
+                    float pw = 1.f;
+#pragma unroll
+                    for (int j = 0; j < kMaxNI; ++j) {
+                        const float a = pw * v.x, b = pw * v.y;
+                        if (j < p.NI && p.cm[j] >= 0) {
+                            xs[p.cm[j] + k] = a;
+                            xs[p.K + p.cm[j] + k] = b;
+                        }
+                        if (j < p.NI && p.cc[j] >= 0) {
+                            xs[p.cc[j] + k] = a;
+                            xs[p.K + p.cc[j] + k] = -b;
+                        }
+                        pw *= s2;
+                    }
+                }
+            }
+            if (part == 0) {
+                xs[p.K - 1] = 1.f;
+                xs[2 * p.K - 1] = 0.f;
+                xs[2 * p.K] = tv.x;
+                xs[2 * p.K + 1] = tv.y;
+            }
+        } else {
+            for (int f = part; f < p.D; f += kLsWaves) xs[f] = 0.f;
+        }
+        __syncthreads();
+        if (m0 + kLsTile < send) fetch(m0 + kLsTile);
+        // tile (I, J) += X[:, 16I..16I+15]^T X[:, 16J..16J+15], 4 samples per step:
+        // lane l feeds row / column l % 16 of sample l / 16 of the step.  The
+        // step is the outer loop, so consecutive matrix-core operations go to
+        // different accumulators (independent); a scheduling barrier per step
+        // keeps the LDS operands of one step, not all 16, in registers.
+        const int r = lane >> 4, c = lane & 15;
+#pragma unroll
+        for (int kk = 0; kk < kLsTile / 4; ++kk) {
+            const float *xr = X[4 * kk + r];
+#pragma unroll
+            for (int u = 0; u < MAXP; ++u)
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[16 * pI[u] + c], xr[16 * pJ[u] + c], acc[u], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // tile element (4 (l / 16) + v, l % 16) is in register v of lane l
+    float *out = p.partials + (slab * p.npairs) * 256;
+#pragma unroll
+    for (int u = 0; u < MAXP; ++u) {
+        if (u < mine) {
+            float *o = out + (int64_t)(wv + kLsWaves * u) * 256;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[(4 * (lane >> 4) + v) * 16 + (lane & 15)] = acc[u][v];
+        }
+    }
+}
+
+// First level: FP64 sums of the partials of kLsGroup consecutive slabs.
+__global__ void __launch_bounds__(kBlock) ls_reduce1_kernel(const float *__restrict__ partials, int64_t nslabs,
+                                                            int64_t E, double *__restrict__ r1)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= E) return;
+    const int64_t g = blockIdx.y;
+    const int64_t s1 = std::min<int64_t>(nslabs, (g + 1) * kLsGroup);
+    double t = 0.0;
+    for (int64_t sl = g * kLsGroup; sl < s1; ++sl) t += (double)partials[sl * E + e];
+    r1[g * E + e] = t;
+}
+
+// Second level: sum the groups in order and scatter the tile element into the
+// full symmetric R (Dp x Dp, FP64).
+__global__ void __launch_bounds__(kBlock) ls_reduce2_kernel(const double *__restrict__ r1, int64_t groups, int64_t E,
+                                                            int nt, int Dp, double *__restrict__ R)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= E) return;
+    double t = 0.0;
+    for (int64_t g = 0; g < groups; ++g) t += r1[g * E + e];
+    int I, J;
+    ls_pair((int)(e / 256), nt, I, J);
+    const int i = 16 * I + (int)((e % 256) / 16), j = 16 * J + (int)(e % 16);
+    R[(int64_t)i * Dp + j] = t;
+    R[(int64_t)j * Dp + i] = t;
+}
+
+// A (K x K) and b (K) from R.
+__global__ void __launch_bounds__(kBlock) ls_assemble_kernel(const double *__restrict__ R, int K, int Dp,
+                                                             double2 *__restrict__ A, double2 *__restrict__ b)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < (int64_t)K * K) {
+        const int a = (int)(e / K), c = (int)(e % K);
+        const double re = R[(int64_t)a * Dp + c] + R[(int64_t)(K + a) * Dp + K + c];
+        const double im = R[(int64_t)a * Dp + K + c] - R[(int64_t)(K + a) * Dp + c];
+        A[e] = make_double2(re, im);
+    } else if (e < (int64_t)K * K + K) {
+        const int a = (int)(e - (int64_t)K * K);
+        const int tr = 2 * K, ti = 2 * K + 1;
+        const double re = R[(int64_t)a * Dp + tr] + R[(int64_t)(K + a) * Dp + ti];
+        const double im = R[(int64_t)a * Dp + ti] - R[(int64_t)(K + a) * Dp + tr];
+        b[a] = make_double2(re, im);
+    }
+}
+
+// Sum over the 64 lanes of a wave in FP64 (fixed butterfly: every lane gets
+// the same total).
+__device__ __forceinline__ double ls_wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Cholesky solve of (A + delta I) h = b in FP64 by one wave: left-looking
+// columns (the pivot's sum by a lane-strided dot product and a butterfly, the
+// column below the diagonal one row per lane), then the two triangular solves
+// with lane-parallel dot products.  delta = ridge * mean(Re diag A).  info =
+// 0, or j + 1 when the pivot of column j is not positive (h is then NaN).
+__global__ void __launch_bounds__(64) ls_solve_kernel(const double2 *__restrict__ A, const double2 *__restrict__ b,
+                                                      int K, double ridge, double2 *__restrict__ Lm,
+                                                      double2 *__restrict__ yv, float2 *__restrict__ h,
+                                                      int32_t *__restrict__ info)
+{
+    const int lane = threadIdx.x;
+    double tr = 0.0;
+    for (int i = lane; i < K; i += 64) tr += A[(int64_t)i * K + i].x;
+    const double delta = ridge * ls_wave_sum(tr) / K;
+    for (int64_t e = lane; e < (int64_t)K * K; e += 64) {
+        double2 v = A[e];
+        if (e / K == e % K) v.x += delta;
+        Lm[e] = v;
+    }
+    __syncthreads();
+    for (int j = 0; j < K; ++j) {
+        const double2 *Lj = Lm + (int64_t)j * K;
+        double d = 0.0;
+        for (int k = lane; k < j; k += 64) d += Lj[k].x * Lj[k].x + Lj[k].y * Lj[k].y;
+        const double piv = Lj[j].x - ls_wave_sum(d);
+        if (!(piv > 0.0)) {
+            for (int i = lane; i < K; i += 64) h[i] = make_float2(NAN, NAN);
+            if (lane == 0) *info = j + 1;
+            return;
+        }
+        const double inv = 1.0 / sqrt(piv);
+        for (int i = j + 1 + lane; i < K; i += 64) {
+            double2 *Li = Lm + (int64_t)i * K;
+            double2 s = Li[j];
+            for (int k = 0; k < j; ++k) {
+                const double2 a = Li[k], c = Lj[k];
+                // s -= a * conj(c)
+                s.x -= a.x * c.x + a.y * c.y;
+                s.y -= a.y * c.x - a.x * c.y;
+            }
+            Li[j] = make_double2(s.x * inv, s.y * inv);
+        }
+        __syncthreads();
+        if (lane == 0) Lm[(int64_t)j * K + j] = make_double2(sqrt(piv), 0.0);
+        __syncthreads();
+    }
+    // L y = b
+    for (int i = 0; i < K; ++i) {
+        const double2 *Li = Lm + (int64_t)i * K;
+        double sr = 0.0, si = 0.0;
+        for (int k = lane; k < i; k += 64) {
+            const double2 a = Li[k], y = yv[k];
+            sr += a.x * y.x - a.y * y.y;
+            si += a.x * y.y + a.y * y.x;
+        }
+        sr = ls_wave_sum(sr);
+        si = ls_wave_sum(si);
+        if (lane == 0) {
+            const double d = Li[i].x;
+            yv[i] = make_double2((b[i].x - sr) / d, (b[i].y - si) / d);
+        }
+        __syncthreads();
+    }
+    // L^H h = y   (L^H[i][k] = conj(L[k][i])); yv[k] holds h_k for k > i
+    for (int i = K - 1; i >= 0; --i) {
+        double sr = 0.0, si = 0.0;
+        for (int k = i + 1 + lane; k < K; k += 64) {
+            const double2 a = Lm[(int64_t)k * K + i], x = yv[k];
+            // conj(a) * x
+            sr += a.x * x.x + a.y * x.y;
+            si += a.x * x.y - a.y * x.x;
+        }
+        sr = ls_wave_sum(sr);
+        si = ls_wave_sum(si);
+        if (lane == 0) {
+            const double d = Lm[(int64_t)i * K + i].x;
+            yv[i] = make_double2((yv[i].x - sr) / d, (yv[i].y - si) / d);
+        }
+        __syncthreads();
+    }
+    for (int i = lane; i < K; i += 64) h[i] = make_float2((float)yv[i].x, (float)yv[i].y);
+    if (lane == 0) *info = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) ls_zero_kernel(double2 *__restrict__ p, int64_t count)
+{
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e < count) p[e] = make_double2(0.0, 0.0);
+}
+
+typedef void (*LsGramKernel)(LsParams);
+
+template <int... P>
+static const LsGramKernel *ls_gram_table_of(std::integer_sequence<int, P...>)
+{
+    static const LsGramKernel t[] = {&ls_gram_kernel<P + 1>...};
+    return t;
+}
+
+static const LsGramKernel *ls_gram_table()
+{
+    return ls_gram_table_of(std::make_integer_sequence<int, kLsPairsPerWave>{});
+}
+
+struct LsShape {
+    int K, D, Dp, nt, npairs;
+};
+
+static LsShape ls_shape(const CoefMap &map)
+{
+    LsShape s;
+    s.K = (map.n_main + map.n_conj) * map.L + 1;
+    s.D = 2 * s.K + 2;
+    s.Dp = (s.D + 15) / 16 * 16;
+    s.nt = s.Dp / 16;
+    s.npairs = s.nt * (s.nt + 1) / 2;
+    return s;
+}
+
+struct LsWs {
+    size_t partials, r1, R, total;
+};
+
+static LsWs ls_ws(const LsShape &s, int64_t rows, int64_t n)
+{
+    const int64_t spr = (n + kLsSlab - 1) / kLsSlab;
+    const int64_t nslabs = std::max<int64_t>(rows * spr, 1);
+    const int64_t groups = (nslabs + kLsGroup - 1) / kLsGroup;
+    const int64_t E = (int64_t)s.npairs * 256;
+    auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    LsWs w;
+    w.partials = up((size_t)(nslabs * E) * sizeof(float));
+    w.r1 = up((size_t)(groups * E) * sizeof(double));
+    w.R = up((size_t)s.Dp * s.Dp * sizeof(double));
+    w.total = w.partials + w.r1 + w.R;
+    return w;
+}
+
+}  // namespace dpd
+
+using namespace dpd;
+
+DPD_EXPORT dpd_status dpd_ls_ws_size(const dpd_plan *plan, int64_t rows, int64_t n, size_t *bytes)
+{
+    if (plan == nullptr || bytes == nullptr || rows < 0 || n < 0) return DPD_EINVAL;
+    const LsShape s = ls_shape(plan->map);
+    if (s.Dp > kLsMaxDp) return DPD_EUNSUPPORTED;
+    *bytes = ls_ws(s, rows, n).total;
+    return DPD_OK;
+}
+
+DPD_EXPORT dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y, const void *t, int64_t rows,
+                                    int64_t n, int64_t ld, float y_scale, void *ws, size_t ws_bytes, void *A,
+                                    void *b)
+{
+    if (plan == nullptr || A == nullptr || b == nullptr) return DPD_EINVAL;
+    if (rows == 1 && ld < n) ld = n;
+    if (n < 0 || rows < 0 || (rows > 1 && ld < n) || !std::isfinite(y_scale)) return DPD_EINVAL;
+    const CoefMap &map = plan->map;
+    const LsShape s = ls_shape(map);
+    if (s.Dp > kLsMaxDp) return DPD_EUNSUPPORTED;
+    const LsWs w = ls_ws(s, rows, n);
+    if (ws == nullptr || ws_bytes < w.total || (uintptr_t)ws % 256 != 0) return DPD_EINVAL;
+    for (const void *q : {y, t, (const void *)A, (const void *)b})
+        if ((uintptr_t)q % 8 != 0) return DPD_EINVAL;
+    if (rows * n > 0 && (y == nullptr || t == nullptr)) return DPD_EINVAL;
+    const hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    float *partials = (float *)base;
+    double *r1 = (double *)(base + w.partials);
+    double *R = (double *)(base + w.partials + w.r1);
+    const int64_t spr = (n + kLsSlab - 1) / kLsSlab;
+    const int64_t nslabs = rows * spr;
+    const int64_t E = (int64_t)s.npairs * 256;
+    hipError_t e = hipSuccess;
+    if (nslabs == 0) {
+        // no samples: A = 0, b = 0 (a fill kernel, not a memset: capturable)
+        const int64_t kk = (int64_t)s.K * s.K;
+        hipLaunchKernelGGL(ls_zero_kernel, dim3((uint32_t)((kk + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           (double2 *)A, kk);
+        hipLaunchKernelGGL(ls_zero_kernel, dim3((uint32_t)((s.K + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           (double2 *)b, (int64_t)s.K);
+        e = hipGetLastError();
+        return e == hipSuccess ? DPD_OK : hip_fail(e);
+    }
+    LsParams p;
+    p.y = (const float2 *)y;
+    p.t = (const float2 *)t;
+    p.n = n;
+    p.ld = ld;
+    p.slabs_per_row = spr;
+    p.y_scale = y_scale;
+    p.partials = partials;
+    p.K = s.K;
+    p.D = s.D;
+    p.Dp = s.Dp;
+    p.nt = s.nt;
+    p.npairs = s.npairs;
+    p.L = map.L;
+    p.NI = map.NI;
+    for (int j = 0; j < kMaxNI; ++j) {
+        p.cm[j] = (int16_t)(map.main_idx[j] >= 0 ? map.main_idx[j] * map.L : -1);
+        p.cc[j] = (int16_t)(map.conj_idx[j] >= 0 ? (map.n_main + map.conj_idx[j]) * map.L : -1);
+    }
+    if (nslabs >= ((int64_t)1 << 31)) return DPD_EUNSUPPORTED;
+    const int per_wave = (s.npairs + kLsWaves - 1) / kLsWaves;
+    hipLaunchKernelGGL(ls_gram_table()[per_wave - 1], dim3((uint32_t)nslabs), dim3(kBlock), 0, st, p);
+    e = hipGetLastError();
+    const int64_t groups = (nslabs + kLsGroup - 1) / kLsGroup;
+    const uint32_t eb = (uint32_t)((E + kBlock - 1) / kBlock);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(ls_reduce1_kernel, dim3(eb, (uint32_t)groups), dim3(kBlock), 0, st,
+                           (const float *)partials, nslabs, E, r1);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(ls_reduce2_kernel, dim3(eb), dim3(kBlock), 0, st, (const double *)r1, groups, E, s.nt,
+                           s.Dp, R);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        const int64_t outs = (int64_t)s.K * s.K + s.K;
+        hipLaunchKernelGGL(ls_assemble_kernel, dim3((uint32_t)((outs + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           (const double *)R, s.K, s.Dp, (double2 *)A, (double2 *)b);
+        e = hipGetLastError();
+    }
+    return e == hipSuccess ? DPD_OK : hip_fail(e);
+}
+
+DPD_EXPORT dpd_status dpd_ls_solve_ws_size(int32_t K, size_t *bytes)
+{
+    if (K < 1 || bytes == nullptr) return DPD_EINVAL;
+    *bytes = ((size_t)K * K + K) * sizeof(double2);
+    return DPD_OK;
+}
+
+DPD_EXPORT dpd_status dpd_ls_solve(void *stream, int32_t K, const void *A, const void *b, double ridge, void *ws,
+                                   size_t ws_bytes, void *h, void *info)
+{
+    if (K < 1 || A == nullptr || b == nullptr || h == nullptr || info == nullptr || ws == nullptr) return DPD_EINVAL;
+    if (!(ridge >= 0.0) || !std::isfinite(ridge)) return DPD_EINVAL;
+    if (ws_bytes < ((size_t)K * K + K) * sizeof(double2)) return DPD_EINVAL;
+    for (const void *q : {A, b, (const void *)ws})
+        if ((uintptr_t)q % 16 != 0) return DPD_EINVAL;
+    if ((uintptr_t)h % 8 != 0 || (uintptr_t)info % 4 != 0) return DPD_EINVAL;
+    double2 *Lm = (double2 *)ws;
+    double2 *yv = Lm + (size_t)K * K;
+    hipLaunchKernelGGL(ls_solve_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, (const double2 *)A,
+                       (const double2 *)b, K, ridge, Lm, yv, (float2 *)h, (int32_t *)info);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DPD_OK : hip_fail(e);
+}

@@ -73,6 +73,10 @@ _SIGS = {
     "dpd_loss_grad": [_vp, _vp, _vp, _i64, ctypes.c_float, _vp, _vp, _vp, ctypes.c_size_t],
     "dpd_adam_step": [_vp, _vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float,
                       ctypes.c_float, ctypes.c_float],
+    "dpd_ls_ws_size": [_vp, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+    "dpd_ls_normal": [_vp, _vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, _vp, ctypes.c_size_t, _vp, _vp],
+    "dpd_ls_solve_ws_size": [_i32, ctypes.POINTER(ctypes.c_size_t)],
+    "dpd_ls_solve": [_vp, _i32, _vp, _vp, ctypes.c_double, _vp, ctypes.c_size_t, _vp, _vp],
 }
 
 # Symbols the header declares (checked by the CPU test-suite).
@@ -252,6 +256,51 @@ def dpd_adam_step(stream, p_ptr, g_ptr, m_ptr, v_ptr, count, step, lr, beta1=0.9
                                float(beta1), float(beta2), float(eps)), "dpd_adam_step")
 
 
+def dpd_ls_ws_size(plan, rows, n) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().dpd_ls_ws_size(plan, int(rows), int(n), ctypes.byref(b)), "dpd_ls_ws_size")
+    return b.value
+
+
+def dpd_ls_normal(plan, stream, y_ptr, t_ptr, rows, n, ld, y_scale, ws_ptr, ws_bytes, a_ptr, b_ptr):
+    _check(lib().dpd_ls_normal(plan, stream, y_ptr, t_ptr, int(rows), int(n), int(ld), float(y_scale), ws_ptr,
+                               int(ws_bytes), a_ptr, b_ptr), "dpd_ls_normal")
+
+
+def dpd_ls_solve_ws_size(K) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().dpd_ls_solve_ws_size(int(K), ctypes.byref(b)), "dpd_ls_solve_ws_size")
+    return b.value
+
+
+def dpd_ls_solve(stream, K, a_ptr, b_ptr, ridge, ws_ptr, ws_bytes, h_ptr, info_ptr):
+    _check(lib().dpd_ls_solve(stream, int(K), a_ptr, b_ptr, float(ridge), ws_ptr, int(ws_bytes), h_ptr,
+                              info_ptr), "dpd_ls_solve")
+
+
+def ls_solve(A, b, ridge=0.0):
+    """Cholesky solve of (A + ridge * mean(diag A) I) h = b on the device.
+    A: (K, K) complex128 GPU tensor (Hermitian), b: (K,) complex128.  Returns
+    (h complex64 (K,), info int32 GPU scalar: 0 = ok, j+1 = not positive
+    definite at column j)."""
+    torch = _torch()
+    if (not isinstance(A, torch.Tensor) or not A.is_cuda or A.dtype != torch.complex128 or A.dim() != 2
+            or A.shape[0] != A.shape[1]):
+        raise TypeError("A must be a square complex128 GPU tensor")
+    K = A.shape[0]
+    if not isinstance(b, torch.Tensor) or not b.is_cuda or b.dtype != torch.complex128 or b.numel() != K:
+        raise TypeError("b must be a complex128 GPU tensor of K values")
+    A = A.contiguous()
+    b = b.contiguous()
+    h = torch.empty(K, dtype=torch.complex64, device=A.device)
+    info = torch.empty((), dtype=torch.int32, device=A.device)
+    wsb = dpd_ls_solve_ws_size(K)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=A.device)
+    dpd_ls_solve(current_stream(), K, A.data_ptr(), b.data_ptr(), ridge, ws.data_ptr(), wsb, h.data_ptr(),
+                 info.data_ptr())
+    return h, info
+
+
 # ------------------------------------------------------- tensor wrappers ---
 
 def _torch():
@@ -377,3 +426,24 @@ class Plan:
                      gx.data_ptr() if gx is not None else 0, gc.data_ptr() if gc is not None else 0,
                      rows, n, ld, ws.data_ptr(), ws_bytes)
         return gx, gc
+
+    def ls_normal(self, y, t, y_scale=1.0):
+        """Normal equations (Psi^H Psi, Psi^H t) of the least-squares fit of
+        this plan's basis on input y_scale * y to target t (section 2.2,
+        Eq. 2): (K, K) and (K,) complex128 GPU tensors.  y, t: complex64,
+        1-D or rows x n."""
+        torch = _torch()
+        y = _dev_c64(y, "y")
+        t = _dev_c64(t, "t")
+        y2 = y.reshape(1, -1) if y.dim() == 1 else y
+        t2 = t.reshape(1, -1) if t.dim() == 1 else t
+        if y2.shape != t2.shape or y2.stride() != t2.stride() or y2.stride(1) != 1:
+            raise ValueError("y and t must have the same row-major layout")
+        rows, n, ld = y2.shape[0], y2.shape[1], y2.stride(0)
+        A = torch.empty((self.K, self.K), dtype=torch.complex128, device=y.device)
+        b = torch.empty(self.K, dtype=torch.complex128, device=y.device)
+        wsb = dpd_ls_ws_size(self.handle, rows, n)
+        ws = torch.empty(max(wsb, 256), dtype=torch.uint8, device=y.device)
+        dpd_ls_normal(self.handle, current_stream(), y2.data_ptr(), t2.data_ptr(), rows, n, ld, y_scale,
+                      ws.data_ptr(), wsb, A.data_ptr(), b.data_ptr())
+        return A, b

@@ -72,3 +72,19 @@ def test_null_arguments(lib):
     assert lib.dpd_num_coeffs(None, None) == dpd.DPD_EINVAL
     assert lib.dpd_batch_create(None, 0, None, ctypes.byref(h)) == dpd.DPD_EINVAL
     assert lib.dpd_batch_destroy(None) == dpd.DPD_OK
+
+
+def test_least_squares_argument_checks(lib):
+    sz = ctypes.c_size_t()
+    assert lib.dpd_ls_ws_size(None, 1, 10, ctypes.byref(sz)) == dpd.DPD_EINVAL
+    assert lib.dpd_ls_normal(None, None, None, None, 1, 10, 10, ctypes.c_float(1.0), None, 0, None,
+                             None) == dpd.DPD_EINVAL
+    assert lib.dpd_ls_solve_ws_size(0, ctypes.byref(sz)) == dpd.DPD_EINVAL
+    assert lib.dpd_ls_solve_ws_size(33, ctypes.byref(sz)) == dpd.DPD_OK
+    assert sz.value == (33 * 33 + 33) * 16          # L (K x K) and y (K), complex128
+    assert lib.dpd_ls_solve(None, 0, None, None, ctypes.c_double(0.0), None, 0, None, None) == dpd.DPD_EINVAL
+    fake = ctypes.c_void_p(4096)                    # never dereferenced: rejected before any launch
+    assert lib.dpd_ls_solve(None, 3, fake, fake, ctypes.c_double(-1.0), fake, 1 << 20, fake,
+                            fake) == dpd.DPD_EINVAL  # negative ridge
+    assert lib.dpd_ls_solve(None, 3, fake, fake, ctypes.c_double(0.0), fake, 16, fake,
+                            fake) == dpd.DPD_EINVAL  # workspace too small
