@@ -247,11 +247,17 @@ __device__ __forceinline__ double ls_wave_sum(double v)
 // column below the diagonal one row per lane), then the two triangular solves
 // with lane-parallel dot products.  delta = ridge * mean(Re diag A).  info =
 // 0, or j + 1 when the pivot of column j is not positive (h is then NaN).
+// LDS: the factor and y live in dynamic shared memory (K <= 63: at most 64 KB)
+// instead of the workspace, so each column's dependent reads are LDS reads.
+template <bool LDS>
 __global__ void __launch_bounds__(64) ls_solve_kernel(const double2 *__restrict__ A, const double2 *__restrict__ b,
-                                                      int K, double ridge, double2 *__restrict__ Lm,
-                                                      double2 *__restrict__ yv, float2 *__restrict__ h,
+                                                      int K, double ridge, double2 *__restrict__ Lg,
+                                                      double2 *__restrict__ yg, float2 *__restrict__ h,
                                                       int32_t *__restrict__ info)
 {
+    extern __shared__ double2 ls_smem[];
+    double2 *Lm = LDS ? ls_smem : Lg;
+    double2 *yv = LDS ? ls_smem + (int64_t)K * K : yg;
     const int lane = threadIdx.x;
     double tr = 0.0;
     for (int i = lane; i < K; i += 64) tr += A[(int64_t)i * K + i].x;
@@ -489,8 +495,13 @@ DPD_EXPORT dpd_status dpd_ls_solve(void *stream, int32_t K, const void *A, const
     if ((uintptr_t)h % 8 != 0 || (uintptr_t)info % 4 != 0) return DPD_EINVAL;
     double2 *Lm = (double2 *)ws;
     double2 *yv = Lm + (size_t)K * K;
-    hipLaunchKernelGGL(ls_solve_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, (const double2 *)A,
-                       (const double2 *)b, K, ridge, Lm, yv, (float2 *)h, (int32_t *)info);
+    const size_t lds = ((size_t)K * K + K) * sizeof(double2);
+    if (lds <= 65536)
+        hipLaunchKernelGGL(ls_solve_kernel<true>, dim3(1), dim3(64), lds, (hipStream_t)stream, (const double2 *)A,
+                           (const double2 *)b, K, ridge, Lm, yv, (float2 *)h, (int32_t *)info);
+    else
+        hipLaunchKernelGGL(ls_solve_kernel<false>, dim3(1), dim3(64), 0, (hipStream_t)stream, (const double2 *)A,
+                           (const double2 *)b, K, ridge, Lm, yv, (float2 *)h, (int32_t *)info);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? DPD_OK : hip_fail(e);
 }

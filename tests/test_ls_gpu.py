@@ -125,8 +125,10 @@ def test_deterministic(torch, dpd):
     assert torch.equal(A1, A2) and torch.equal(b1, b2)
 
 
-def test_solve_matches_numpy(torch, dpd, orc):
-    mo, co, L, n = [1, 3, 5, 7], [1, 3, 5, 7], 4, 20000
+@pytest.mark.parametrize("mo,co,L", [([1, 3, 5, 7], [1, 3, 5, 7], 4),          # K = 33: factor in LDS
+                                     ([1, 3, 5, 7, 9], [1, 3, 5, 7, 9], 8)])   # K = 81: factor in the workspace
+def test_solve_matches_numpy(torch, dpd, orc, mo, co, L):
+    n = 20000
     y, t = _target(n, mo, co, L, seed=2)
     Ar, br = orc.ls_normal(y, mo, co, L, t)
     Ad = torch.from_numpy(Ar).cuda()
