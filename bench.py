@@ -212,6 +212,34 @@ def leg_backward(torch, dpd, signals, steps=50):
             "valu_frac_nonpacked": round(flops * n / (kmean * 1e-3) / 1e12 / VALU_FP32_NONPACKED_TFLOPS, 4)}
 
 
+# The paper's Table 4 peak throughputs for the Table 2 configuration (32-bit
+# float; mobile SoCs of 2014-2015): context for the table2 leg, not a target.
+PAPER_TABLE4_MSPS = {"Tegra K1 GPU (Kepler, 852 MHz)": 153.5, "Tegra X1 GPU (Maxwell, 998 MHz)": 221.8,
+                     "TK1 4x Cortex-A15 NEON+OpenMP": 214.4, "TX1 4x Cortex-A57 NEON+OpenMP": 200.1}
+
+
+def leg_table2(torch, dpd, signals, steps=200):
+    """The paper's Table 2 configuration (section 3.4): P = 5 main, Q = 3
+    conjugate, L = 5, DC term, on N = 2^24 OFDM-like samples."""
+    mo, co, L, n = [1, 3, 5], [1, 3], 5, 1 << 24
+    x_host = signals.ofdm_16qam(n, config_id=2)
+    plan = dpd.Plan(mo, co, L, signals.aph_coeffs(mo, co, L, config_id=2))
+    xs, zs = _rotating(torch, x_host)
+    st = dpd.current_stream()
+    ptrs = [(a.data_ptr(), b.data_ptr()) for a, b in zip(xs, zs)]
+    wall, kmean = _time_launches(
+        torch, lambda i: dpd.dpd_apply(plan.handle, st, ptrs[i][0], ptrs[i][1], n), len(xs), steps, 200)
+    msps = n / (kmean * 1e-3) / 1e6
+    gbs = BYTES_PER_SAMPLE * n / (kmean * 1e-3) / 1e9
+    del xs, zs
+    best = max(PAPER_TABLE4_MSPS.values())
+    return {"workload": "Table 2 configuration: orders {1,3,5} main, {1,3} conjugate, L=5, DC; N=2^24",
+            "kernel_ms": round(kmean, 4), "msamples_per_s": round(msps, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "tune": plan.get_tune(),
+            "paper_table4_msamples_per_s": PAPER_TABLE4_MSPS,
+            "ratio_to_best_paper_number": round(msps / best, 1)}
+
+
 def leg_ls(torch, dpd, signals, reps=5):
     """Least-squares estimation (section 2.2, Eq. 2) with the headline basis
     (orders {1,3,5,7} both branches, L = 4, K = 33): the matrix-core normal
@@ -248,8 +276,17 @@ def leg_ls(torch, dpd, signals, reps=5):
         del y, t, ws
     h, info = dpd.ls_solve(A, b, 1e-9)
     out["solve_us"] = round(autotune.time_us(lambda: dpd.ls_solve(A, b, 1e-9), warmup=2, iters=reps), 1)
+    from paper_1612_09001_amd import spectral
+
     x = torch.from_numpy(signals.ofdm_16qam(1 << 18, config_id=5, rms=0.2)).cuda()
     est = ila.ILA(x, orders, orders, L)
+    xh = x.cpu().numpy()
+
+    def regrowth():
+        _, y = est.transmit()
+        return round(spectral.distortion_regrowth_db(y.cpu().numpy() / est.pa.gain, xh), 2)
+
+    out["guard_band_distortion_db_no_dpd"] = regrowth()
     e = [est.nmse_db()]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -261,6 +298,7 @@ def leg_ls(torch, dpd, signals, reps=5):
         est.step()
         e.append(est.nmse_db())
     out["ila_nmse_db_iters_0_to_3"] = [round(v, 2) for v in e]
+    out["guard_band_distortion_db_after_3_iters"] = regrowth()
     out["ila_solve_info"] = int(est.info.item())
     return out
 
@@ -321,7 +359,7 @@ def main():
                     help="also run one plain device copy of the same bytes (counter calibration)")
     ap.add_argument("--only-leg", default="",
                     help="run only these secondary workloads (comma-separated: config3, config4, backward, "
-                         "config5, ls) and print their results, e.g. under a profiler")
+                         "config5, ls, table2) and print their results, e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU only; --gpus %d is not supported (the forward map, the "
@@ -332,7 +370,7 @@ def main():
     import torch
     from paper_1612_09001_amd import dpd, signals
     legs = {"config3": leg_config3, "config4": leg_config4, "backward": leg_backward, "config5": leg_config5,
-            "ls": leg_ls}
+            "ls": leg_ls, "table2": leg_table2}
     if args.only_leg:
         for name in args.only_leg.split(","):
             if name not in legs:

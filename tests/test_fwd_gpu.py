@@ -224,3 +224,27 @@ def test_config3_full_size_sampled(torch, dpd, orc):
     T = 256 * plan.get_tune()["samples_per_thread"]
     idx = _sample_idx(n, T, np.random.default_rng(3))
     assert_parity(z[idx], orc.forward_at(x, mo, co, L, h, idx), "config3")
+
+
+def _table2():
+    """The paper's Table 2 configuration, from tests/golden/table2_config.txt."""
+    import os
+
+    cfg = {}
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table2_config.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, *v = line.split()
+                cfg[k] = [int(t) for t in v]
+    return cfg["main_orders"], cfg["conj_orders"], cfg["L"][0]
+
+
+@pytest.mark.parametrize("tune", [(8, 1), (4, 0)])
+def test_table2_configuration(torch, dpd, orc, tune):
+    """Section 3.4 / Table 2: P = 5 main, Q = 3 conjugate (I_Q a proper subset
+    of I_P), L = 5, DC term -- the configuration of the paper's Table 4."""
+    mo, co, L = _table2()
+    x = signals.ofdm_16qam(200003, config_id=2)
+    h = signals.aph_coeffs(mo, co, L, config_id=2)
+    z = _run(torch, dpd, x, mo, co, L, h, tune)
+    assert_parity(z, orc.forward(x, mo, co, L, h), "table2 %s" % (tune,))

@@ -67,3 +67,17 @@ def test_batch_specs():
     assert set(s[1] for s in specs) <= {5, 7, 9}
     assert set(s[2] for s in specs) <= set(range(2, 9))
     assert specs == signals.batch_specs()
+
+
+def test_table2_fixture():
+    """The Table 2 configuration fixture parses to P = 5, Q = 3, L = 5 (K = 26)."""
+    import os
+
+    cfg = {}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table2_config.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            cfg[k] = [int(t) for t in v]
+    assert cfg["main_orders"] == [1, 3, 5] and cfg["conj_orders"] == [1, 3] and cfg["L"] == [5]
+    assert signals.num_coeffs(cfg["main_orders"], cfg["conj_orders"], cfg["L"][0]) == 26
