@@ -240,6 +240,56 @@ def leg_table2(torch, dpd, signals, steps=200):
             "ratio_to_best_paper_number": round(msps / best, 1)}
 
 
+def leg_ingest(torch, dpd, signals, reps=3):
+    """Host ingestion: 2^25 samples from pinned host memory through the
+    headline predistorter back to pinned host memory (chunks of 2^22 on two
+    streams, copies overlapped with filtering); the host-link-bound rate, never
+    the headline value."""
+    from paper_1612_09001_amd import ingest
+
+    orders, L, n = [1, 3, 5, 7], 4, 1 << 25
+    plan = dpd.Plan(orders, orders, L, signals.aph_coeffs(orders, orders, L, config_id=1))
+    xh = torch.from_numpy(signals.ofdm_16qam(n, config_id=1)).pin_memory()
+    zh = torch.empty(n, dtype=torch.complex64).pin_memory()
+    out = {"workload": "pinned host -> predistorter (headline basis) -> pinned host, 2^25 samples"}
+    for chunk in (1 << 20, 1 << 22):
+        pipe = ingest.HostPipeline(plan, chunk=chunk)
+        pipe.run(xh, zh)
+        ts = []
+        for _ in range(reps):
+            pipe.reset()
+            t0 = time.perf_counter()
+            pipe.run(xh, zh)
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        out["chunk_2^%d" % (chunk.bit_length() - 1)] = {
+            "ms": round(t * 1e3, 2), "msamples_per_s": round(n / t / 1e6, 1),
+            "host_link_gbs_each_way": round(8 * n / t / 1e9, 2)}
+        del pipe
+    # the same copies with no filtering (the host-link ceiling of this pattern)
+    chunk = 1 << 22
+    ss = [torch.cuda.Stream(), torch.cuda.Stream()]
+    bufs = [torch.empty(chunk, dtype=torch.complex64, device="cuda") for _ in ss]
+
+    def copies():
+        for i, t0 in enumerate(range(0, n, chunk)):
+            with torch.cuda.stream(ss[i % 2]):
+                bufs[i % 2].copy_(xh[t0:t0 + chunk], non_blocking=True)
+                zh[t0:t0 + chunk].copy_(bufs[i % 2], non_blocking=True)
+        for q in ss:
+            q.synchronize()
+
+    copies()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        copies()
+        ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
+    out["copies_only_chunk_2^22"] = {"ms": round(t * 1e3, 2), "host_link_gbs_each_way": round(8 * n / t / 1e9, 2)}
+    return out
+
+
 def leg_ls(torch, dpd, signals, reps=5):
     """Least-squares estimation (section 2.2, Eq. 2) with the headline basis
     (orders {1,3,5,7} both branches, L = 4, K = 33): the matrix-core normal
@@ -359,7 +409,7 @@ def main():
                     help="also run one plain device copy of the same bytes (counter calibration)")
     ap.add_argument("--only-leg", default="",
                     help="run only these secondary workloads (comma-separated: config3, config4, backward, "
-                         "config5, ls, table2) and print their results, e.g. under a profiler")
+                         "config5, ls, table2, ingest) and print their results, e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU only; --gpus %d is not supported (the forward map, the "
@@ -370,7 +420,7 @@ def main():
     import torch
     from paper_1612_09001_amd import dpd, signals
     legs = {"config3": leg_config3, "config4": leg_config4, "backward": leg_backward, "config5": leg_config5,
-            "ls": leg_ls, "table2": leg_table2}
+            "ls": leg_ls, "table2": leg_table2, "ingest": leg_ingest}
     if args.only_leg:
         for name in args.only_leg.split(","):
             if name not in legs:

@@ -1,0 +1,69 @@
+"""Host ingestion: predistort a stream held in pinned host memory.
+
+The paper's mobile GPUs read the samples in place from zero-copy host memory
+(section 3.3.1); on a discrete GPU the samples cross the host link instead.
+``HostPipeline`` cuts the stream into chunks and, on two streams of default
+priority, overlaps the host-to-device copy of one chunk and the device-to-host
+copy of another with the filtering of a third.  Each chunk is filtered by
+``dpd_apply_hist`` with the L-1 samples before it carried on the device, so
+the chunked result equals one call over the whole stream; the filtering of
+consecutive chunks is chained by events, the copies are not.  PyTorch supplies
+the pinned buffers, device buffers, streams and copies; the filtering is
+libdpd's.
+"""
+from __future__ import annotations
+
+from . import dpd as _dpd
+
+
+class HostPipeline:
+    def __init__(self, plan, chunk: int = 1 << 22, nbuf: int = 2):
+        import torch
+
+        if chunk < 1 or nbuf < 1:
+            raise ValueError("chunk and nbuf must be positive")
+        self.torch = torch
+        self.plan = plan
+        self.chunk = int(chunk)
+        self.nbuf = int(nbuf)
+        self.streams = [torch.cuda.Stream() for _ in range(self.nbuf)]
+        self.din = [torch.empty(self.chunk, dtype=torch.complex64, device="cuda") for _ in range(self.nbuf)]
+        self.dout = [torch.empty(self.chunk, dtype=torch.complex64, device="cuda") for _ in range(self.nbuf)]
+        self.hist = torch.zeros(max(plan.L - 1, 1), dtype=torch.complex64, device="cuda")
+
+    def reset(self):
+        """Forget the carried history (the next run starts from zeros)."""
+        self.hist.zero_()
+        self.torch.cuda.synchronize()
+
+    def run(self, x_host, z_host):
+        """z_host[:] = predistorter(x_host); both pinned complex64 host tensors
+        of the same length.  Returns after the last copy has landed."""
+        torch = self.torch
+        if (x_host.dtype != torch.complex64 or z_host.dtype != torch.complex64 or x_host.is_cuda
+                or z_host.is_cuda or x_host.numel() != z_host.numel()):
+            raise TypeError("x_host and z_host must be host complex64 tensors of one length")
+        if not (x_host.is_pinned() and z_host.is_pinned()):
+            raise ValueError("host buffers must be pinned (torch pin_memory=True)")
+        x = x_host.reshape(-1)
+        z = z_host.reshape(-1)
+        n = x.numel()
+        hp = self.hist.data_ptr() if self.plan.L > 1 else 0
+        torch.cuda.current_stream().synchronize()   # the history and buffers are ready
+        prev = None
+        for i, t0 in enumerate(range(0, n, self.chunk)):
+            b = i % self.nbuf
+            s = self.streams[b]
+            m = min(self.chunk, n - t0)
+            with torch.cuda.stream(s):
+                self.din[b][:m].copy_(x[t0:t0 + m], non_blocking=True)
+                if prev is not None:
+                    s.wait_event(prev)
+                _dpd.dpd_apply_hist(self.plan.handle, s.cuda_stream, self.din[b].data_ptr(),
+                                    self.dout[b].data_ptr(), m, hp)
+                prev = torch.cuda.Event()
+                prev.record(s)
+                z[t0:t0 + m].copy_(self.dout[b][:m], non_blocking=True)
+        for s in self.streams:
+            s.synchronize()
+        return z_host
