@@ -199,3 +199,50 @@ def test_indirect_learning_linearizes_the_synthetic_pa(torch, dpd):
     assert e0 > -25.0 and errs[0] <= -45.0 and errs[-1] <= -45.0, (e0, errs)
     # section 5.2 reports > 10 dB suppression of the spectral spurs
     assert r1 <= r0 - 10.0, (r0, r1)
+
+
+def test_graph_replay(torch, dpd):
+    """dpd_ls_normal and dpd_ls_solve allocate nothing and launch only kernels
+    (no memset), so they replay from a captured graph; every replay, with eager
+    work in between, equals the eager result bitwise."""
+    mo, co, L, n = [1, 3, 5, 7], [1, 3, 5, 7], 4, 30000
+    y, t = _target(n, mo, co, L, seed=11)
+    plan = dpd.Plan(mo, co, L, signals.aph_coeffs(mo, co, L))
+    yd, td = _dev(torch, y), _dev(torch, t)
+    K = plan.K
+    A = torch.empty((K, K), dtype=torch.complex128, device="cuda")
+    b = torch.empty(K, dtype=torch.complex128, device="cuda")
+    h = torch.empty(K, dtype=torch.complex64, device="cuda")
+    info = torch.empty((), dtype=torch.int32, device="cuda")
+    wsb = dpd.dpd_ls_ws_size(plan.handle, 1, n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    swsb = dpd.dpd_ls_solve_ws_size(K)
+    sws = torch.empty(swsb, dtype=torch.uint8, device="cuda")
+
+    def run():
+        st = dpd.current_stream()
+        dpd.dpd_ls_normal(plan.handle, st, yd.data_ptr(), td.data_ptr(), 1, n, n, 1.0, ws.data_ptr(), wsb,
+                          A.data_ptr(), b.data_ptr())
+        dpd.dpd_ls_solve(st, K, A.data_ptr(), b.data_ptr(), 1e-9, sws.data_ptr(), swsb, h.data_ptr(),
+                         info.data_ptr())
+
+    run()
+    torch.cuda.synchronize()
+    ref_a, ref_h = A.clone(), h.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        run()                      # warm-up on the capture stream
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            run()
+    torch.cuda.synchronize()
+    for r in range(4):
+        A.fill_(complex(r, -r))     # eager work between replays
+        h.fill_(0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(A, ref_a) and torch.equal(h, ref_h), "replay %d" % r
+        assert int(info.item()) == 0
