@@ -193,8 +193,17 @@ __global__ void __launch_bounds__(kBlock) ls_reduce1_kernel(const float *__restr
     if (e >= E) return;
     const int64_t g = blockIdx.y;
     const int64_t s1 = std::min<int64_t>(nslabs, (g + 1) * kLsGroup);
+    // eight loads in flight at a time, the sum in slab order
     double t = 0.0;
-    for (int64_t sl = g * kLsGroup; sl < s1; ++sl) t += (double)partials[sl * E + e];
+    int64_t sl = g * kLsGroup;
+    for (; sl + 8 <= s1; sl += 8) {
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = partials[(sl + i) * E + e];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) t += (double)v[i];
+    }
+    for (; sl < s1; ++sl) t += (double)partials[sl * E + e];
     r1[g * E + e] = t;
 }
 
@@ -206,7 +215,15 @@ __global__ void __launch_bounds__(kBlock) ls_reduce2_kernel(const double *__rest
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= E) return;
     double t = 0.0;
-    for (int64_t g = 0; g < groups; ++g) t += r1[g * E + e];
+    int64_t g = 0;
+    for (; g + 8 <= groups; g += 8) {
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = r1[(g + i) * E + e];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) t += v[i];
+    }
+    for (; g < groups; ++g) t += r1[g * E + e];
     int I, J;
     ls_pair((int)(e / 256), nt, I, J);
     const int i = 16 * I + (int)((e % 256) / 16), j = 16 * J + (int)(e % 16);
