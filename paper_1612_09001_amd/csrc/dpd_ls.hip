@@ -15,9 +15,10 @@
 // R is a dense contraction over samples, so it runs on the matrix cores:
 // v_mfma_f32_16x16x4f32 over 16x16 tiles of the upper triangle of R, the
 // features of 64 samples at a time staged in LDS.  Each block covers one slab
-// of 4096 samples and writes its FP32 tiles (at most 1024 products per
-// accumulator); the slabs are summed in FP64 in a fixed order (two levels),
-// so the result is deterministic.
+// of 1024..4096 samples (the size depends only on the input shape and the
+// number of CUs) and writes its FP32 tiles (at most 1024 four-product steps
+// per accumulator); the slabs are summed in FP64 in a fixed order (two
+// levels), so the result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,7 +35,8 @@ namespace dpd {
 typedef float v4f_ls __attribute__((ext_vector_type(4)));
 
 constexpr int kLsTile = 64;         // samples staged per step
-constexpr int kLsSlab = 4096;       // samples per block / FP32 partial
+constexpr int kLsSlabMax = 4096;    // samples per block / FP32 partial (at most)
+constexpr int kLsSlabMin = 1024;
 constexpr int kLsMaxDp = 192;       // padded real features (2K+2 rounded up to 16): K <= 95
 constexpr int kLsMaxNt = kLsMaxDp / 16;
 constexpr int kLsMaxPairs = kLsMaxNt * (kLsMaxNt + 1) / 2;
@@ -48,6 +50,7 @@ struct LsParams {
     const float2 *t;        // target, same layout
     int64_t n, ld;
     int64_t slabs_per_row;
+    int64_t slab;           // samples per block (a multiple of kLsTile)
     float y_scale;          // the basis is built from y_scale * y
     float *partials;        // [slab][pair][256]
     int K, D, Dp, nt, npairs;
@@ -79,7 +82,7 @@ __global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t slab = blockIdx.x;
     const int64_t row = slab / p.slabs_per_row;
-    const int64_t s0 = (slab - row * p.slabs_per_row) * kLsSlab;
+    const int64_t s0 = (slab - row * p.slabs_per_row) * p.slab;
     const float2 *yr = p.y + row * p.ld;
     const float2 *tr = p.t + row * p.ld;
     const int pad = p.Dp - p.D;
@@ -99,7 +102,7 @@ __global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
 
     const int s = tid & (kLsTile - 1);   // sample of the tile this thread builds
     const int part = tid / kLsTile;      // taps part, part + 4, ...
-    const int64_t send = std::min<int64_t>(s0 + kLsSlab, p.n);
+    const int64_t send = std::min<int64_t>(s0 + p.slab, p.n);
     // The samples a thread needs for a tile (y_{m-k} for its taps, t_m) are
     // loaded one tile ahead, during the previous tile's matrix-core phase.
     constexpr int KT = kMaxL / kLsWaves;
@@ -388,9 +391,21 @@ struct LsWs {
     size_t partials, r1, R, total;
 };
 
+// Samples per block: 4096 on large inputs; smaller (down to 1024) when that
+// leaves fewer than ~6 blocks per CU, so small fits still fill the chip.
+int num_cus();
+static int64_t ls_slab(int64_t rows, int64_t n)
+{
+    const int64_t want = (int64_t)num_cus() * 6;
+    int64_t slab = kLsSlabMax;
+    while (slab > kLsSlabMin && rows * ((n + slab - 1) / slab) < want) slab /= 2;
+    return slab;
+}
+
 static LsWs ls_ws(const LsShape &s, int64_t rows, int64_t n)
 {
-    const int64_t spr = (n + kLsSlab - 1) / kLsSlab;
+    const int64_t slab = ls_slab(rows, n);
+    const int64_t spr = (n + slab - 1) / slab;
     const int64_t nslabs = std::max<int64_t>(rows * spr, 1);
     const int64_t groups = (nslabs + kLsGroup - 1) / kLsGroup;
     const int64_t E = (int64_t)s.npairs * 256;
@@ -436,7 +451,8 @@ DPD_EXPORT dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y,
     float *partials = (float *)base;
     double *r1 = (double *)(base + w.partials);
     double *R = (double *)(base + w.partials + w.r1);
-    const int64_t spr = (n + kLsSlab - 1) / kLsSlab;
+    const int64_t slab = ls_slab(rows, n);
+    const int64_t spr = (n + slab - 1) / slab;
     const int64_t nslabs = rows * spr;
     const int64_t E = (int64_t)s.npairs * 256;
     hipError_t e = hipSuccess;
@@ -456,6 +472,7 @@ DPD_EXPORT dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y,
     p.n = n;
     p.ld = ld;
     p.slabs_per_row = spr;
+    p.slab = slab;
     p.y_scale = y_scale;
     p.partials = partials;
     p.K = s.K;
