@@ -108,7 +108,10 @@ dpd_status dpd_get_tune(const dpd_plan *plan, dpd_tune *tune);
 
 /* ---------------------------------------------------------------- forward --
  * dpd_apply -- Eq. (1) / Algorithm 1 on one stream of n samples with zero
- * pre-history: out[t] = z_t for t = 0..n-1.  in, out: device complex64.
+ * pre-history: out[t] = z_t for t = 0..n-1.  in, out: device complex64 (device
+ * memory, or the device mapping of pinned host memory from
+ * hipHostGetDevicePointer: the zero-copy form of section 3.3.1, where the
+ * kernel reads and writes across the host link).
  * n == 0 is a no-op returning DPD_OK. */
 dpd_status dpd_apply(dpd_plan *plan, void *stream, const void *in, void *out, int64_t n);
 

@@ -53,3 +53,28 @@ def test_rejects_pageable_buffers(torch):
     pipe = ingest.HostPipeline(plan, chunk=1024)
     with pytest.raises(ValueError):
         pipe.run(torch.zeros(10, dtype=torch.complex64), torch.zeros(10, dtype=torch.complex64))
+
+
+def test_zero_copy_matches_oracle_and_device_call(torch, orc):
+    from paper_1612_09001_amd import dpd, ingest
+
+    mo, co = [1, 3, 5, 7], [1, 3]
+    L, n = 5, 1000003
+    x = signals.ofdm_16qam(n, config_id=82)
+    h = signals.aph_coeffs(mo, co, L, config_id=82)
+    plan = dpd.Plan(mo, co, L, h)
+    xh = torch.from_numpy(x).pin_memory()
+    zh = torch.zeros(n, dtype=torch.complex64).pin_memory()
+    ingest.ZeroCopy(plan).run(xh, zh)
+    z1 = zh.numpy().copy()
+    assert_parity(z1, orc.forward(x, mo, co, L, h), "zero-copy")
+    zd = plan.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.array_equal(z1, zd)
+
+
+def test_zero_copy_rejects_pageable(torch):
+    from paper_1612_09001_amd import dpd, ingest
+
+    plan = dpd.Plan([1], [], 2, np.array([1, 0, 0], np.complex64))
+    with pytest.raises(ValueError):
+        ingest.ZeroCopy(plan).run(torch.zeros(10, dtype=torch.complex64), torch.zeros(10, dtype=torch.complex64))
