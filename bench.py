@@ -11,11 +11,13 @@ the 256 MB last-level cache cannot serve repeated steps.
 Prints ONE JSON line: throughput, the HBM roofline of the kernel (algorithmic
 bytes / kernel time from HIP events on the launch stream), the FP64 oracle
 timed on the host (which also gates accuracy) and, under "secondary", the
-other workloads: the two-carrier N = 2^26 stream (orders to 9, L = 8), the
-256-stream batch (persistent launch vs per-stream launches) and the
-coefficient-learning step (fused kernels vs autograd vs plain-ops autograd).
+other workloads: the launch-bound N = 65,536 stream, the two-carrier N = 2^26
+stream (orders to 9, L = 8), the 256-stream batch (persistent launch vs
+per-stream launches), the adjoint, the coefficient-learning step (fused
+kernels vs autograd vs plain-ops autograd), least-squares estimation and
+indirect learning, the paper's Table 2 configuration and host ingestion.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--main-only]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--main-only] [--only-leg NAME]
 """
 from __future__ import annotations
 
@@ -125,6 +127,57 @@ def _time_launches(torch, launch, nbuf, steps, warmup):
     return wall, e0.elapsed_time(e1) / steps
 
 
+def leg_config1(torch, dpd, signals, steps=2000, graph_len=100, singles=200):
+    """The small configuration: one stream of N = 65,536 samples, the headline
+    basis (orders {1,3,5,7} both branches, L = 4, DC).  Its 1 MiB of traffic
+    takes 0.13 us at HBM peak, so launch overhead bounds it: back-to-back
+    launches, the same launches replayed from one hipGraph, and the latency of
+    one launch followed by a stream synchronisation."""
+    from paper_1612_09001_amd import autotune
+
+    orders, L, n = [1, 3, 5, 7], 4, 65536
+    plan = dpd.Plan(orders, orders, L, signals.aph_coeffs(orders, orders, L, config_id=1))
+    x = torch.from_numpy(signals.ofdm_16qam(n, config_id=1)).cuda()
+    z = torch.empty_like(x)
+    st = dpd.current_stream()
+    default_ms = _time_launches(
+        torch, lambda i: dpd.dpd_apply(plan.handle, st, x.data_ptr(), z.data_ptr(), n), 1, steps, 200)[1]
+    tune = autotune.tune_plan(plan, x, out=z)
+    wall, launch_ms = _time_launches(
+        torch, lambda i: dpd.dpd_apply(plan.handle, st, x.data_ptr(), z.data_ptr(), n), 1, steps, 200)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        sc = dpd.current_stream()
+        for _ in range(graph_len):
+            dpd.dpd_apply(plan.handle, sc, x.data_ptr(), z.data_ptr(), n)
+    for _ in range(5):
+        g.replay()
+    torch.cuda.synchronize()
+    reps = max(1, steps // graph_len)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_us = e0.elapsed_time(e1) * 1e3 / (reps * graph_len)
+    lat = []
+    for _ in range(singles):
+        t0 = time.perf_counter()
+        dpd.dpd_apply(plan.handle, st, x.data_ptr(), z.data_ptr(), n)
+        torch.cuda.current_stream().synchronize()
+        lat.append(time.perf_counter() - t0)
+    lat_us = float(np.median(lat)) * 1e6
+    return {"workload": "single stream N=65536, orders {1,3,5,7} main+conj, L=4, DC (launch-bound)",
+            "tune": tune, "back_to_back_us_per_apply_default_tune": round(default_ms * 1e3, 2),
+            "back_to_back_us_per_apply": round(launch_ms * 1e3, 2),
+            "back_to_back_msamples_per_s": round(n / (launch_ms * 1e-3) / 1e6, 1),
+            "graph_us_per_apply": round(graph_us, 2),
+            "graph_msamples_per_s": round(n / (graph_us * 1e-6) / 1e6, 1),
+            "launch_plus_sync_latency_us_median": round(lat_us, 1),
+            "hbm_time_at_peak_us": round(BYTES_PER_SAMPLE * n / (HBM_PEAK_GBS * 1e9) * 1e6, 3)}
+
+
 def leg_config3(torch, dpd, signals, steps=50):
     """N = 2^26 two-carrier stream, orders {1..9} both branches, L = 8."""
     orders = [1, 3, 5, 7, 9]
@@ -174,6 +227,11 @@ def leg_config4(torch, dpd, signals, reps=20):
     flops = sum(n * (8 * ((pmax + 1) // 2) * L + 3) for n, pmax, L in wl.specs)
     t_hbm = BYTES_PER_SAMPLE * total / (HBM_PEAK_GBS * 1e9) * 1e6
     t_valu = flops / (VALU_FP32_NONPACKED_TFLOPS * 1e12) * 1e6
+    # each stream at the larger of its own two times: the bound when streams
+    # of different classes do not overlap memory and ALU work with each other
+    t_cls = sum(max(BYTES_PER_SAMPLE * n / (HBM_PEAK_GBS * 1e9),
+                    n * (8 * ((pmax + 1) // 2) * L + 3) / (VALU_FP32_NONPACKED_TFLOPS * 1e12))
+                for n, pmax, L in wl.specs) * 1e6
     return {"workload": "256 streams, n~U[2^14,2^20] (seeded), P_max in {5,7,9}, L in {2..8}, conj+DC",
             "samples": total, "tune": tune, "chunks_blocks": list(b.info()),
             "persistent_graph_us": round(t_graph, 1), "persistent_us": round(t_direct, 1),
@@ -182,6 +240,7 @@ def leg_config4(torch, dpd, signals, reps=20):
             "flops_per_sample": round(flops / total, 1),
             "valu_frac_nonpacked": round(flops / (t_graph * 1e-6) / 1e12 / VALU_FP32_NONPACKED_TFLOPS, 4),
             "bound_us": round(max(t_hbm, t_valu), 1), "bound_frac": round(max(t_hbm, t_valu) / t_graph, 4),
+            "per_stream_bound_us": round(t_cls, 1), "per_stream_bound_frac": round(t_cls / t_graph, 4),
             "speedup_vs_per_stream": round(t_each / t_graph, 2),
             "speedup_vs_per_stream_graph": round(t_graph_each / t_graph, 2)}
 
@@ -337,7 +396,11 @@ def leg_ls(torch, dpd, signals, reps=5):
         out["normal_2^%d_mfma_frac" % lg] = round(issued * n / (us * 1e-6) / 1e12 / MFMA_FP32_TFLOPS, 4)
         del y, t, ws
     h, info = dpd.ls_solve(A, b, 1e-9)
-    out["solve_us"] = round(autotune.time_us(lambda: dpd.ls_solve(A, b, 1e-9), warmup=2, iters=reps), 1)
+    swsb = dpd.dpd_ls_solve_ws_size(K)
+    sws = torch.empty(swsb, dtype=torch.uint8, device="cuda")
+    out["solve_us"] = round(autotune.time_us(
+        lambda: dpd.dpd_ls_solve(st, K, A.data_ptr(), b.data_ptr(), 1e-9, sws.data_ptr(), swsb, h.data_ptr(),
+                                 info.data_ptr()), warmup=2, iters=max(reps, 20)), 1)
     from paper_1612_09001_amd import spectral
 
     x = torch.from_numpy(signals.ofdm_16qam(1 << 18, config_id=5, rms=0.2)).cuda()
@@ -420,8 +483,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain device copy of the same bytes (counter calibration)")
     ap.add_argument("--only-leg", default="",
-                    help="run only these secondary workloads (comma-separated: config3, config4, backward, "
-                         "config5, ls, table2, ingest) and print their results, e.g. under a profiler")
+                    help="run only these secondary workloads (comma-separated: config1, config3, config4, "
+                         "backward, config5, ls, table2, ingest) and print their results, e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU only; --gpus %d is not supported (the forward map, the "
@@ -431,7 +494,7 @@ def main():
 
     import torch
     from paper_1612_09001_amd import dpd, signals
-    legs = {"config3": leg_config3, "config4": leg_config4, "backward": leg_backward, "config5": leg_config5,
+    legs = {"config1": leg_config1, "config3": leg_config3, "config4": leg_config4, "backward": leg_backward, "config5": leg_config5,
             "ls": leg_ls, "table2": leg_table2, "ingest": leg_ingest}
     if args.only_leg:
         for name in args.only_leg.split(","):

@@ -240,8 +240,9 @@ dpd_status dpd_adam_step(void *stream, float *params, const float *grads, float 
  *   rows x n at stride ld samples (ld >= n; ignored when rows == 1), 8-byte
  *   aligned.  ws: device, >= dpd_ls_ws_size bytes, 256-byte aligned,
  *   caller-owned scratch.  A, b: device, 8-byte aligned, overwritten.  FP32
- *   products accumulated in FP32 over slabs of 4096 samples, the slabs summed
- *   in FP64 in a fixed order: deterministic.  Allocates nothing, does not
+ *   products accumulated in FP32 over slabs of 1024 to 4096 samples (the size
+ *   depends only on rows, n and the device's CU count), the slabs summed in
+ *   FP64 in a fixed order: deterministic.  Allocates nothing, does not
  *   synchronize; rows * n == 0 gives A = 0, b = 0. */
 dpd_status dpd_ls_ws_size(const dpd_plan *plan, int64_t rows, int64_t n, size_t *bytes);
 dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y, const void *t, int64_t rows,
@@ -254,7 +255,8 @@ dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y, const void
  *   complex64 (the section 2.2 stacking, ready for dpd_set_coeffs_device).
  *   info: device int32, set to 0 on success or j+1 when the pivot of column j
  *   is not positive (h is then NaN); the host sees it after synchronizing.
- *   ws: device, >= dpd_ls_solve_ws_size bytes, 16-byte aligned. */
+ *   ws: device, >= dpd_ls_solve_ws_size bytes (K*K complex128), 16-byte
+ *   aligned.  One wavefront; DPD_EUNSUPPORTED for K > 1024. */
 dpd_status dpd_ls_solve_ws_size(int32_t K, size_t *bytes);
 dpd_status dpd_ls_solve(void *stream, int32_t K, const void *A, const void *b, double ridge, void *ws,
                         size_t ws_bytes, void *h, void *info);

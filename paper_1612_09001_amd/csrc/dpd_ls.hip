@@ -35,6 +35,7 @@ namespace dpd {
 typedef float v4f_ls __attribute__((ext_vector_type(4)));
 
 constexpr int kLsTile = 64;         // samples staged per step
+constexpr int kLsSolveMaxK = 1024;  // one wave, at most 16 rows per lane
 constexpr int kLsSlabMax = 4096;    // samples per block / FP32 partial (at most)
 constexpr int kLsSlabMin = 1024;
 constexpr int kLsMaxDp = 192;       // padded real features (2K+2 rounded up to 16): K <= 95
@@ -262,93 +263,208 @@ __device__ __forceinline__ double ls_wave_sum(double v)
     return v;
 }
 
-// Cholesky solve of (A + delta I) h = b in FP64 by one wave: left-looking
-// columns (the pivot's sum by a lane-strided dot product and a butterfly, the
-// column below the diagonal one row per lane), then the two triangular solves
-// with lane-parallel dot products.  delta = ridge * mean(Re diag A).  info =
-// 0, or j + 1 when the pivot of column j is not positive (h is then NaN).
-// LDS: the factor and y live in dynamic shared memory (K <= 63: at most 64 KB)
-// instead of the workspace, so each column's dependent reads are LDS reads.
-template <bool LDS>
+// v of lane `src` (wave-uniform) in every lane, through scalar registers.
+__device__ __forceinline__ double ls_bcast(double v, int src)
+{
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), src);
+    const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Cholesky solve of (A + delta I) h = b in FP64 by one wave, delta = ridge *
+// mean(Re diag A).  Lane l owns rows l, l + 64, ... (R slots).  The factor is
+// stored by columns, F[k ld + r] = L[r][k] (ld = 64 in LDS, where K <= 64,
+// else K), zero above the diagonal, so the lanes read one column at
+// consecutive addresses and the entries of row j are broadcasts.
+// Left-looking: for column j every owned row r >= j forms
+//   s_r = A[r][j] - sum_{k<j} L[r][k] conj(L[j][k]),
+// G k per step into up to four partial sums.  The diagonal of A + delta I stays in
+// its owner's registers and F's diagonal holds zero until L[j][j] is written,
+// so the row-j factor of every k >= j reads zero: the last step of a column
+// needs no mask.  s_j is the pivot (taken from its owner lane), L[j][j] =
+// sqrt(s_j) and the rows below store s_r / L[j][j].  The triangular solves
+// sweep columns: once y_j (then h_j) is final its owner broadcasts it and
+// every row still open subtracts its multiple, the next column's entries
+// already loading.  Loads use row indices clamped into the matrix (every
+// value read is finite), so the inner loops have no per-lane branches; only
+// rows a lane owns are stored.  info = 0, or j + 1 when the pivot of column
+// j is not positive (h is then NaN).
+template <bool LDS, int R>
 __global__ void __launch_bounds__(64) ls_solve_kernel(const double2 *__restrict__ A, const double2 *__restrict__ b,
-                                                      int K, double ridge, double2 *__restrict__ Lg,
-                                                      double2 *__restrict__ yg, float2 *__restrict__ h,
-                                                      int32_t *__restrict__ info)
+                                                      int K, double ridge, double2 *__restrict__ Fg,
+                                                      float2 *__restrict__ h, int32_t *__restrict__ info)
 {
     extern __shared__ double2 ls_smem[];
-    double2 *Lm = LDS ? ls_smem : Lg;
-    double2 *yv = LDS ? ls_smem + (int64_t)K * K : yg;
+    double2 *F = LDS ? ls_smem : Fg;
+    const int ld = LDS ? 64 : K;
     const int lane = threadIdx.x;
+    int rc[R];   // owned rows clamped into the matrix (loads only)
+#pragma unroll
+    for (int t = 0; t < R; ++t) rc[t] = min(lane + 64 * t, K - 1);
     double tr = 0.0;
     for (int i = lane; i < K; i += 64) tr += A[(int64_t)i * K + i].x;
     const double delta = ridge * ls_wave_sum(tr) / K;
-    for (int64_t e = lane; e < (int64_t)K * K; e += 64) {
-        double2 v = A[e];
-        if (e / K == e % K) v.x += delta;
-        Lm[e] = v;
+    double dg[R];   // Re A[r][r] + delta of the owned rows
+#pragma unroll
+    for (int t = 0; t < R; ++t) dg[t] = A[(int64_t)rc[t] * K + rc[t]].x + delta;
+    // F = strict lower triangle of A (row r, column k), zero elsewhere; U
+    // columns of loads in flight
+    constexpr int U = R <= 2 ? 8 : (R <= 4 ? 4 : 2);
+    for (int k0 = 0; k0 < K; k0 += U) {
+        double2 v[U][R];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const int r = lane + 64 * t, k = k0 + u;
+                v[u][t] = (k < K && r > k && r < K) ? A[(int64_t)r * K + k] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int t = 0; t < R; ++t) {
+                const int r = lane + 64 * t, k = k0 + u;
+                if (k < K && r < K) F[k * ld + r] = v[u][t];
+            }
     }
     __syncthreads();
+
+    // k per step of the column sums (fewer when a lane owns more rows)
+    constexpr int G = R == 1 ? 8 : (R == 2 ? 4 : (R == 4 ? 2 : 1));
     for (int j = 0; j < K; ++j) {
-        const double2 *Lj = Lm + (int64_t)j * K;
-        double d = 0.0;
-        for (int k = lane; k < j; k += 64) d += Lj[k].x * Lj[k].x + Lj[k].y * Lj[k].y;
-        const double piv = Lj[j].x - ls_wave_sum(d);
+        constexpr int P = G >= 4 ? 4 : G;   // partial sums per row
+        double2 s[P][R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            s[0][t] = F[j * ld + rc[t]];
+            if (lane + 64 * t == j) s[0][t].x += dg[t];
+#pragma unroll
+            for (int e = 1; e < P; ++e) s[e][t] = make_double2(0.0, 0.0);
+        }
+        for (int k = 0; k < j; k += G) {
+            double2 c[G], a[G][R];
+            if (k + G <= K) {   // every column of the step exists
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    c[q] = F[(k + q) * ld + j];                                      // L[j][k]
+#pragma unroll
+                    for (int t = 0; t < R; ++t) a[q][t] = F[(k + q) * ld + rc[t]];  // L[r][k]
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < G; ++q) {
+                    const int kc = min(k + q, K - 1);
+                    c[q] = F[kc * ld + j];
+#pragma unroll
+                    for (int t = 0; t < R; ++t) a[q][t] = F[kc * ld + rc[t]];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);   // every load of the step in flight first
+#pragma unroll
+            for (int q = 0; q < G; ++q)
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    double2 &acc = s[q % P][t];
+                    // acc -= a * conj(c)
+                    acc.x = fma(-a[q][t].x, c[q].x, acc.x);
+                    acc.x = fma(-a[q][t].y, c[q].y, acc.x);
+                    acc.y = fma(-a[q][t].y, c[q].x, acc.y);
+                    acc.y = fma(a[q][t].x, c[q].y, acc.y);
+                }
+        }
+        double mine = 0.0;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+#pragma unroll
+            for (int e = 1; e < P; ++e) {
+                s[0][t].x += s[e][t].x;
+                s[0][t].y += s[e][t].y;
+            }
+            if (t == (j >> 6)) mine = s[0][t].x;
+        }
+        const double piv = ls_bcast(mine, j & 63);
         if (!(piv > 0.0)) {
             for (int i = lane; i < K; i += 64) h[i] = make_float2(NAN, NAN);
             if (lane == 0) *info = j + 1;
             return;
         }
-        const double inv = 1.0 / sqrt(piv);
-        for (int i = j + 1 + lane; i < K; i += 64) {
-            double2 *Li = Lm + (int64_t)i * K;
-            double2 s = Li[j];
-            for (int k = 0; k < j; ++k) {
-                const double2 a = Li[k], c = Lj[k];
-                // s -= a * conj(c)
-                s.x -= a.x * c.x + a.y * c.y;
-                s.y -= a.y * c.x - a.x * c.y;
+        const double d = sqrt(piv), inv = 1.0 / d;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int r = lane + 64 * t;
+            if (r == j)
+                F[j * ld + r] = make_double2(d, 0.0);
+            else if (r > j && r < K)
+                F[j * ld + r] = make_double2(s[0][t].x * inv, s[0][t].y * inv);
+        }
+        __syncthreads();
+    }
+
+    // L y = b, then L^H h = y, both on the rows' registers
+    double invd[R];   // 1 / L[r][r] of the owned rows
+#pragma unroll
+    for (int t = 0; t < R; ++t) invd[t] = 1.0 / F[rc[t] * ld + rc[t]].x;
+    double2 y[R], f[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int r = lane + 64 * t;
+        y[t] = r < K ? b[r] : make_double2(0.0, 0.0);
+        f[t] = F[rc[t]];   // column 0
+    }
+    for (int j = 0; j < K; ++j) {
+        double2 fn[R];
+        const int jn = min(j + 1, K - 1);
+#pragma unroll
+        for (int t = 0; t < R; ++t) fn[t] = F[jn * ld + rc[t]];   // L[r][j+1]
+        double2 mine = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+            if (t == (j >> 6)) mine = make_double2(y[t].x * invd[t], y[t].y * invd[t]);
+        const double2 yj = make_double2(ls_bcast(mine.x, j & 63), ls_bcast(mine.y, j & 63));
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int r = lane + 64 * t;
+            if (r == j) {
+                y[t] = yj;
+            } else if (r > j) {
+                // y_r -= L[r][j] y_j
+                y[t].x -= f[t].x * yj.x - f[t].y * yj.y;
+                y[t].y -= f[t].x * yj.y + f[t].y * yj.x;
             }
-            Li[j] = make_double2(s.x * inv, s.y * inv);
+            f[t] = fn[t];
         }
-        __syncthreads();
-        if (lane == 0) Lm[(int64_t)j * K + j] = make_double2(sqrt(piv), 0.0);
-        __syncthreads();
     }
-    // L y = b
-    for (int i = 0; i < K; ++i) {
-        const double2 *Li = Lm + (int64_t)i * K;
-        double sr = 0.0, si = 0.0;
-        for (int k = lane; k < i; k += 64) {
-            const double2 a = Li[k], y = yv[k];
-            sr += a.x * y.x - a.y * y.y;
-            si += a.x * y.y + a.y * y.x;
+#pragma unroll
+    for (int t = 0; t < R; ++t) f[t] = F[rc[t] * ld + (K - 1)];   // L[K-1][r]
+    for (int j = K - 1; j >= 0; --j) {
+        double2 fn[R];
+        const int jn = max(j - 1, 0);
+#pragma unroll
+        for (int t = 0; t < R; ++t) fn[t] = F[rc[t] * ld + jn];   // L[j-1][r]
+        double2 mine = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+            if (t == (j >> 6)) mine = make_double2(y[t].x * invd[t], y[t].y * invd[t]);
+        const double2 hj = make_double2(ls_bcast(mine.x, j & 63), ls_bcast(mine.y, j & 63));
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int r = lane + 64 * t;
+            if (r == j) {
+                y[t] = hj;
+            } else if (r < j) {
+                // y_r -= conj(L[j][r]) h_j
+                y[t].x -= f[t].x * hj.x + f[t].y * hj.y;
+                y[t].y -= f[t].x * hj.y - f[t].y * hj.x;
+            }
+            f[t] = fn[t];
         }
-        sr = ls_wave_sum(sr);
-        si = ls_wave_sum(si);
-        if (lane == 0) {
-            const double d = Li[i].x;
-            yv[i] = make_double2((b[i].x - sr) / d, (b[i].y - si) / d);
-        }
-        __syncthreads();
     }
-    // L^H h = y   (L^H[i][k] = conj(L[k][i])); yv[k] holds h_k for k > i
-    for (int i = K - 1; i >= 0; --i) {
-        double sr = 0.0, si = 0.0;
-        for (int k = i + 1 + lane; k < K; k += 64) {
-            const double2 a = Lm[(int64_t)k * K + i], x = yv[k];
-            // conj(a) * x
-            sr += a.x * x.x + a.y * x.y;
-            si += a.x * x.y - a.y * x.x;
-        }
-        sr = ls_wave_sum(sr);
-        si = ls_wave_sum(si);
-        if (lane == 0) {
-            const double d = Lm[(int64_t)i * K + i].x;
-            yv[i] = make_double2((yv[i].x - sr) / d, (yv[i].y - si) / d);
-        }
-        __syncthreads();
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int r = lane + 64 * t;
+        if (r < K) h[r] = make_float2((float)y[t].x, (float)y[t].y);
     }
-    for (int i = lane; i < K; i += 64) h[i] = make_float2((float)yv[i].x, (float)yv[i].y);
     if (lane == 0) *info = 0;
 }
 
@@ -514,7 +630,8 @@ DPD_EXPORT dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y,
 DPD_EXPORT dpd_status dpd_ls_solve_ws_size(int32_t K, size_t *bytes)
 {
     if (K < 1 || bytes == nullptr) return DPD_EINVAL;
-    *bytes = ((size_t)K * K + K) * sizeof(double2);
+    if (K > kLsSolveMaxK) return DPD_EUNSUPPORTED;
+    *bytes = (size_t)K * K * sizeof(double2);
     return DPD_OK;
 }
 
@@ -522,20 +639,31 @@ DPD_EXPORT dpd_status dpd_ls_solve(void *stream, int32_t K, const void *A, const
                                    size_t ws_bytes, void *h, void *info)
 {
     if (K < 1 || A == nullptr || b == nullptr || h == nullptr || info == nullptr || ws == nullptr) return DPD_EINVAL;
+    if (K > kLsSolveMaxK) return DPD_EUNSUPPORTED;
     if (!(ridge >= 0.0) || !std::isfinite(ridge)) return DPD_EINVAL;
-    if (ws_bytes < ((size_t)K * K + K) * sizeof(double2)) return DPD_EINVAL;
+    if (ws_bytes < (size_t)K * K * sizeof(double2)) return DPD_EINVAL;
     for (const void *q : {A, b, (const void *)ws})
         if ((uintptr_t)q % 16 != 0) return DPD_EINVAL;
     if ((uintptr_t)h % 8 != 0 || (uintptr_t)info % 4 != 0) return DPD_EINVAL;
-    double2 *Lm = (double2 *)ws;
-    double2 *yv = Lm + (size_t)K * K;
-    const size_t lds = ((size_t)K * K + K) * sizeof(double2);
-    if (lds <= 65536)
-        hipLaunchKernelGGL(ls_solve_kernel<true>, dim3(1), dim3(64), lds, (hipStream_t)stream, (const double2 *)A,
-                           (const double2 *)b, K, ridge, Lm, yv, (float2 *)h, (int32_t *)info);
+    const bool in_lds = K <= 64;   // F at column stride 64: at most 64 KiB of LDS
+    const size_t lds = (size_t)K * 64 * sizeof(double2);
+    const int slots = (K + 63) / 64;
+    const int R = slots <= 1 ? 1 : slots <= 2 ? 2 : slots <= 4 ? 4 : slots <= 8 ? 8 : 16;
+    const hipStream_t st = (hipStream_t)stream;
+    const double2 *Ad = (const double2 *)A, *bd = (const double2 *)b;
+    double2 *F = (double2 *)ws;
+    float2 *hd = (float2 *)h;
+    int32_t *id = (int32_t *)info;
+    if (in_lds)
+        hipLaunchKernelGGL((ls_solve_kernel<true, 1>), dim3(1), dim3(64), lds, st, Ad, bd, K, ridge, F, hd, id);
+    else if (R == 2)
+        hipLaunchKernelGGL((ls_solve_kernel<false, 2>), dim3(1), dim3(64), 0, st, Ad, bd, K, ridge, F, hd, id);
+    else if (R == 4)
+        hipLaunchKernelGGL((ls_solve_kernel<false, 4>), dim3(1), dim3(64), 0, st, Ad, bd, K, ridge, F, hd, id);
+    else if (R == 8)
+        hipLaunchKernelGGL((ls_solve_kernel<false, 8>), dim3(1), dim3(64), 0, st, Ad, bd, K, ridge, F, hd, id);
     else
-        hipLaunchKernelGGL(ls_solve_kernel<false>, dim3(1), dim3(64), 0, (hipStream_t)stream, (const double2 *)A,
-                           (const double2 *)b, K, ridge, Lm, yv, (float2 *)h, (int32_t *)info);
+        hipLaunchKernelGGL((ls_solve_kernel<false, 16>), dim3(1), dim3(64), 0, st, Ad, bd, K, ridge, F, hd, id);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? DPD_OK : hip_fail(e);
 }

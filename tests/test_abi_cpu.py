@@ -81,10 +81,13 @@ def test_least_squares_argument_checks(lib):
                              None) == dpd.DPD_EINVAL
     assert lib.dpd_ls_solve_ws_size(0, ctypes.byref(sz)) == dpd.DPD_EINVAL
     assert lib.dpd_ls_solve_ws_size(33, ctypes.byref(sz)) == dpd.DPD_OK
-    assert sz.value == (33 * 33 + 33) * 16          # L (K x K) and y (K), complex128
+    assert sz.value == 33 * 33 * 16                 # the factor, K x K complex128
+    assert lib.dpd_ls_solve_ws_size(1025, ctypes.byref(sz)) == dpd.DPD_EUNSUPPORTED
     assert lib.dpd_ls_solve(None, 0, None, None, ctypes.c_double(0.0), None, 0, None, None) == dpd.DPD_EINVAL
     fake = ctypes.c_void_p(4096)                    # never dereferenced: rejected before any launch
     assert lib.dpd_ls_solve(None, 3, fake, fake, ctypes.c_double(-1.0), fake, 1 << 20, fake,
                             fake) == dpd.DPD_EINVAL  # negative ridge
     assert lib.dpd_ls_solve(None, 3, fake, fake, ctypes.c_double(0.0), fake, 16, fake,
                             fake) == dpd.DPD_EINVAL  # workspace too small
+    assert lib.dpd_ls_solve(None, 1025, fake, fake, ctypes.c_double(0.0), fake, 1 << 30, fake,
+                            fake) == dpd.DPD_EUNSUPPORTED  # more rows than one wave holds

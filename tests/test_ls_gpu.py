@@ -143,6 +143,23 @@ def test_solve_matches_numpy(torch, dpd, orc, mo, co, L):
         assert rel <= 1e-6, (ridge, rel)
 
 
+@pytest.mark.parametrize("K", [1, 2, 63, 64, 65, 130, 300])
+def test_solve_random_sizes(torch, dpd, K):
+    """Every row layout of the one-wave solve (1, 2, 4 and 8 rows per lane; the
+    factor in LDS up to K = 64) against numpy on a random Hermitian positive
+    definite matrix."""
+    rng = np.random.default_rng(K)
+    X = rng.standard_normal((2 * K + 8, K)) + 1j * rng.standard_normal((2 * K + 8, K))
+    A = X.conj().T @ X
+    A = (A + A.conj().T) / 2
+    b = rng.standard_normal(K) + 1j * rng.standard_normal(K)
+    h, info = dpd.ls_solve(torch.from_numpy(A).cuda(), torch.from_numpy(b).cuda(), 1e-3)
+    assert int(info.item()) == 0
+    ref = np.linalg.solve(A + 1e-3 * np.mean(np.real(np.diag(A))) * np.eye(K), b)
+    rel = np.linalg.norm(h.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert rel <= 1e-6, rel
+
+
 def test_solve_reports_indefinite(torch, dpd):
     K = 5
     A = -torch.eye(K, dtype=torch.complex128, device="cuda")
