@@ -16,13 +16,15 @@
 // v_mfma_f32_16x16x4f32 over 16x16 tiles of the upper triangle of R, the
 // features of 64 samples at a time staged in LDS.  Each block covers one slab
 // of 1024..4096 samples (the size depends only on the input shape and the
-// number of CUs) and writes its FP32 tiles (at most 1024 four-product steps
-// per accumulator); the slabs are summed in FP64 in a fixed order (two
+// number of CUs) and writes its FP32 tiles (each of the four waves adds at
+// most 256 four-product steps per accumulator; the four partial tiles are
+// summed in FP32); the slabs are summed in FP64 in a fixed order (two
 // levels), so the result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <utility>
 
 #include "dpd.h"
@@ -40,11 +42,8 @@ constexpr int kLsSlabMax = 4096;    // samples per block / FP32 partial (at most
 constexpr int kLsSlabMin = 1024;
 constexpr int kLsMaxDp = 192;       // padded real features (2K+2 rounded up to 16): K <= 95
 constexpr int kLsMaxNt = kLsMaxDp / 16;
-constexpr int kLsMaxPairs = kLsMaxNt * (kLsMaxNt + 1) / 2;
 constexpr int kLsWaves = kBlock / 64;
-constexpr int kLsPairsPerWave = (kLsMaxPairs + kLsWaves - 1) / kLsWaves;
 constexpr int kLsGroup = 64;        // slabs per first-level FP64 sum
-constexpr int kLsStride = kLsMaxDp + 4;   // LDS row stride (floats)
 
 struct LsParams {
     const float2 *y;        // basis input, rows x ld
@@ -71,39 +70,76 @@ __device__ __forceinline__ void ls_pair(int q, int nt, int &I, int &J)
     J = I + q;
 }
 
-// MAXP: tile pairs per wave (ceil(npairs / 4); one instance per count, so
-// the matrix-core loop has no conditionals -- a guarded accumulation becomes a
-// branch whose merge copies every accumulator).  Surplus slots of the last
-// waves accumulate tile (0, 0) and are not written out.
-template <int MAXP>
-__global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
+// Tile pair q of the upper triangle, row-major over (I <= J), at compile time.
+constexpr int ls_pair_i(int q, int nt)
 {
-    __shared__ float X[kLsTile][kLsStride];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t slab = blockIdx.x;
-    const int64_t row = slab / p.slabs_per_row;
-    const int64_t s0 = (slab - row * p.slabs_per_row) * p.slab;
-    const float2 *yr = p.y + row * p.ld;
-    const float2 *tr = p.t + row * p.ld;
-    const int pad = p.Dp - p.D;
-    if (pad > 0)
-        for (int e = tid; e < kLsTile * pad; e += kBlock) X[e / pad][p.D + e % pad] = 0.f;
-
-    // this wave's tiles: pairs wv, wv + 4, ...
-    const int mine = (p.npairs - wv + kLsWaves - 1) / kLsWaves;
-    int pI[MAXP], pJ[MAXP];
-    v4f_ls acc[MAXP];
-#pragma unroll
-    for (int u = 0; u < MAXP; ++u) {
-        pI[u] = pJ[u] = 0;
-        if (u < mine) ls_pair(wv + kLsWaves * u, p.nt, pI[u], pJ[u]);
-        acc[u] = v4f_ls{0.f, 0.f, 0.f, 0.f};
+    int I = 0;
+    while (q >= nt - I) {
+        q -= nt - I;
+        ++I;
     }
+    return I;
+}
+constexpr int ls_pair_j(int q, int nt)
+{
+    int I = 0;
+    while (q >= nt - I) {
+        q -= nt - I;
+        ++I;
+    }
+    return I + q;
+}
+
+// LDS row stride (floats) for NT column tiles: 16 NT + 1.  Small, so that
+// more blocks share a CU; odd, so that the feature stores (one sample per
+// lane) hit distinct banks.  Measured on K = 33 (16 NT = 80): +0 1.75 ms, +1
+// 1.21 ms, +4 1.30 ms, +8 1.48 ms per 2^24 samples.
+constexpr int ls_stride(int nt) { return 16 * nt + 1; }
+
+// One 4-sample step of the pairs Q0, Q0 + 1, ...: the operand blocks of each
+// pair are compile-time constants (forced), so the operands stay in fixed
+// registers.
+template <int NT, int Q0, int... U>
+__device__ __forceinline__ void ls_gram_step(v4f_ls *acc, const float *op, std::integer_sequence<int, U...>)
+{
+    ((acc[U] = __builtin_amdgcn_mfma_f32_16x16x4f32(op[std::integral_constant<int, ls_pair_i(Q0 + U, NT)>::value],
+                                                    op[std::integral_constant<int, ls_pair_j(Q0 + U, NT)>::value],
+                                                    acc[U], 0, 0, 0)),
+     ...);
+}
+
+// Pair groups of the Gram kernel for NT column tiles: one (every wave holds
+// all NT (NT + 1) / 2 tile accumulators) while they fit in 128 registers,
+// else two (two waves per group).
+constexpr int ls_pair_groups(int nt) { return nt * (nt + 1) / 2 * 4 <= 128 ? 1 : 2; }
+
+// One wave's part of a slab.  The waves of pair group G (GK = 4 / GP of
+// them) accumulate the tile pairs [G PP, (G + 1) PP) of the row-major upper
+// triangle, each over every GK-th 4-sample step of each 64-sample tile, so
+// a step loads each 16-column operand block once for all of its pairs.  All
+// four waves build the features of each tile together (barriers).  At the
+// end the GK partial tiles of each pair are summed through LDS (fixed order)
+// and written out.  The pair list is a compile-time constant: the matrix loop
+// has no conditionals (a guarded accumulation becomes a branch whose merge
+// copies every accumulator) and every wave runs the same code.
+template <int NT, int G>
+__device__ __forceinline__ void ls_gram_wave(const LsParams &p, float (*X)[ls_stride(NT)], int64_t slab, int64_t s0,
+                                             int64_t send, const float2 *yr, const float2 *tr)
+{
+    constexpr int NP = NT * (NT + 1) / 2;
+    constexpr int GP = ls_pair_groups(NT);
+    constexpr int GK = kLsWaves / GP;
+    constexpr int PP = (NP + GP - 1) / GP;
+    constexpr int Q0 = G * PP;
+    constexpr int PW = NP - Q0 < PP ? NP - Q0 : PP;   // pairs of this group
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int kw = (tid >> 6) % GK;                   // this wave's steps: kw, kw + GK, ...
+    v4f_ls acc[PW];
+#pragma unroll
+    for (int u = 0; u < PW; ++u) acc[u] = v4f_ls{0.f, 0.f, 0.f, 0.f};
 
     const int s = tid & (kLsTile - 1);   // sample of the tile this thread builds
     const int part = tid / kLsTile;      // taps part, part + 4, ...
-    const int64_t send = std::min<int64_t>(s0 + p.slab, p.n);
     // The samples a thread needs for a tile (y_{m-k} for its taps, t_m) are
     // loaded one tile ahead, during the previous tile's matrix-core phase.
     constexpr int KT = kMaxL / kLsWaves;
@@ -163,29 +199,75 @@ __global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
         __syncthreads();
         if (m0 + kLsTile < send) fetch(m0 + kLsTile);
         // tile (I, J) += X[:, 16I..16I+15]^T X[:, 16J..16J+15], 4 samples per step:
-        // lane l feeds row / column l % 16 of sample l / 16 of the step.  The
-        // step is the outer loop, so consecutive matrix-core operations go to
-        // different accumulators (independent); a scheduling barrier per step
-        // keeps the LDS operands of one step, not all 16, in registers.
+        // lane l feeds row / column l % 16 of sample l / 16 of the step.  A
+        // step's operand blocks are loaded once and feed every pair; a
+        // scheduling barrier per step keeps one step's operands in registers.
         const int r = lane >> 4, c = lane & 15;
 #pragma unroll
-        for (int kk = 0; kk < kLsTile / 4; ++kk) {
-            const float *xr = X[4 * kk + r];
+        for (int i = 0; i < kLsTile / 4 / GK; ++i) {
+            const float *xr = X[4 * (kw + GK * i) + r];
+            float op[NT];   // blocks no pair of the group uses are never loaded
 #pragma unroll
-            for (int u = 0; u < MAXP; ++u)
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[16 * pI[u] + c], xr[16 * pJ[u] + c], acc[u], 0, 0, 0);
+            for (int b = 0; b < NT; ++b) op[b] = xr[16 * b + c];
+            ls_gram_step<NT, Q0>(acc, op, std::make_integer_sequence<int, PW>{});
             __builtin_amdgcn_sched_barrier(0);
         }
     }
-    // tile element (4 (l / 16) + v, l % 16) is in register v of lane l
-    float *out = p.partials + (slab * p.npairs) * 256;
+    // Sum the GK partial tiles of each pair: the four waves put their
+    // accumulators (pair u of their group) in LDS, then the waves of a group
+    // each add up 4 / GK of the register slots, in wave order.  Tile element
+    // (4 (l / 16) + v, l % 16) is register v of lane l.
+    float *buf = &X[0][0];   // 4 x 256 floats (the tile of 64 x ls_stride(NT) >= 1088 floats)
+    float *out = p.partials + (slab * NP + Q0) * 256;
+    const int wv = tid >> 6;
+    for (int u = 0; u < PP; ++u) {
+        __syncthreads();   // the matrix reads of the last tile / the previous pair's sums are done
+        if (u < PW) {
 #pragma unroll
-    for (int u = 0; u < MAXP; ++u) {
-        if (u < mine) {
-            float *o = out + (int64_t)(wv + kLsWaves * u) * 256;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) o[(4 * (lane >> 4) + v) * 16 + (lane & 15)] = acc[u][v];
+            for (int v = 0; v < 4; ++v) buf[wv * 256 + lane * 4 + v] = acc[u][v];
         }
+        __syncthreads();
+        if (u < PW) {
+            constexpr int VPW = 4 / GK;   // register slots per wave
+#pragma unroll
+            for (int vv = 0; vv < VPW; ++vv) {
+                const int v = kw * VPW + vv;
+                float t = 0.f;
+#pragma unroll
+                for (int w = 0; w < GK; ++w) t += buf[(G * GK + w) * 256 + lane * 4 + v];
+                out[u * 256 + (4 * (lane >> 4) + v) * 16 + (lane & 15)] = t;
+            }
+        }
+    }
+}
+
+// Normal equations of one slab of samples: features of 64 samples at a time
+// staged in LDS (rows = samples, ls_stride(NT) floats), then the upper
+// triangle of the real Gram on the matrix cores, FP32 tiles per slab.  One
+// instance per column-tile count NT.
+template <int NT>
+__global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
+{
+    static_assert(kLsTile * ls_stride(NT) >= kLsWaves * 256, "LDS tile too small for the final sums");
+    __shared__ float X[kLsTile][ls_stride(NT)];
+    const int tid = threadIdx.x;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t slab = blockIdx.x;
+    const int64_t row = slab / p.slabs_per_row;
+    const int64_t s0 = (slab - row * p.slabs_per_row) * p.slab;
+    const float2 *yr = p.y + row * p.ld;
+    const float2 *tr = p.t + row * p.ld;
+    const int pad = p.Dp - p.D;
+    if (pad > 0)
+        for (int e = tid; e < kLsTile * pad; e += kBlock) X[e / pad][p.D + e % pad] = 0.f;
+    const int64_t send = std::min<int64_t>(s0 + p.slab, p.n);
+    if constexpr (ls_pair_groups(NT) == 1) {
+        ls_gram_wave<NT, 0>(p, X, slab, s0, send, yr, tr);
+    } else {
+        if (wv < kLsWaves / 2)
+            ls_gram_wave<NT, 0>(p, X, slab, s0, send, yr, tr);
+        else
+            ls_gram_wave<NT, 1>(p, X, slab, s0, send, yr, tr);
     }
 }
 
@@ -485,7 +567,7 @@ static const LsGramKernel *ls_gram_table_of(std::integer_sequence<int, P...>)
 
 static const LsGramKernel *ls_gram_table()
 {
-    return ls_gram_table_of(std::make_integer_sequence<int, kLsPairsPerWave>{});
+    return ls_gram_table_of(std::make_integer_sequence<int, kLsMaxNt>{});
 }
 
 struct LsShape {
@@ -603,8 +685,7 @@ DPD_EXPORT dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y,
         p.cc[j] = (int16_t)(map.conj_idx[j] >= 0 ? (map.n_main + map.conj_idx[j]) * map.L : -1);
     }
     if (nslabs >= ((int64_t)1 << 31)) return DPD_EUNSUPPORTED;
-    const int per_wave = (s.npairs + kLsWaves - 1) / kLsWaves;
-    hipLaunchKernelGGL(ls_gram_table()[per_wave - 1], dim3((uint32_t)nslabs), dim3(kBlock), 0, st, p);
+    hipLaunchKernelGGL(ls_gram_table()[s.nt - 1], dim3((uint32_t)nslabs), dim3(kBlock), 0, st, p);
     e = hipGetLastError();
     const int64_t groups = (nslabs + kLsGroup - 1) / kLsGroup;
     const uint32_t eb = (uint32_t)((E + kBlock - 1) / kBlock);

@@ -11,10 +11,10 @@ pytestmark = pytest.mark.gpu
 
 # Scaled-Frobenius tolerance of the normal equations.  Features are FP32
 # (order 2j+1 by j repeated multiplications: relative error <= ~(2j+2) 2^-24
-# <= 1.2e-6 for order 9); each FP32 accumulator adds at most 1024 four-product
-# steps before the FP64 slab sum (relative error ~ sqrt(1024) 2^-24 = 2e-6 for
-# random rounding, 6e-5 worst case).  2e-5 sits between the typical and the
-# worst case.
+# <= 1.2e-6 for order 9); each FP32 accumulator adds at most 256 four-product
+# steps and the four wave partials of a slab are added in FP32 before the FP64
+# slab sum (relative error ~ sqrt(260) 2^-24 = 1e-6 for random rounding,
+# 1.6e-5 worst case).  2e-5 sits above the worst case.
 LS_REL_MAX = 2e-5
 
 
