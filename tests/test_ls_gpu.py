@@ -67,6 +67,9 @@ CASES = [  # (main orders, conj orders, L, n)
     ([1, 3, 5, 7, 9, 11, 13], [], 2, 5000),     # high orders, main branch only
     ([1, 3, 5], [1, 3, 5], 5, 3),               # fewer samples than taps
     ([1, 3, 5, 7], [1, 3, 5, 7], 6, 65536 + 17),  # config-5 basis, 17 slabs
+    ([1, 3, 5, 7, 9], [1, 3, 5], 5, 3000),      # K = 41: 6 x 6 tiles
+    ([1, 3, 5, 7, 9, 11, 13], [1, 3, 5, 7, 9, 11, 13], 4, 6000),  # K = 57: 8 x 8 tiles, two pair groups
+    ([1, 3, 5, 7, 9, 11, 13, 15], [1, 3, 5], 8, 2500),  # K = 89: 12 x 12 tiles, the largest basis
 ]
 
 
