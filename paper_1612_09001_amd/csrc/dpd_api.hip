@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -179,20 +180,20 @@ __global__ void hist_update_kernel(const float2 *__restrict__ in, int64_t n, flo
 
 // --------------------------------------------------------------- tables ---
 
-// Compute units of the current device (cached per device id).
+// Compute units of the current device (cached per device id; concurrent
+// first calls store the same value).
 int num_cus()
 {
-    static int cache[64] = {0};
+    static std::atomic<int> cache[64] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (cache[dev] == 0) {
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            cus <= 0)
+    int cus = cache[dev].load(std::memory_order_relaxed);
+    if (cus == 0) {
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
             cus = 256;
-        cache[dev] = cus;
+        cache[dev].store(cus, std::memory_order_relaxed);
     }
-    return cache[dev];
+    return cus;
 }
 
 static FwdTable g_fwd;
@@ -341,7 +342,6 @@ DPD_EXPORT dpd_status dpd_destroy(dpd_plan *plan)
     if (plan == nullptr) return DPD_OK;
     hipError_t e = hipDeviceSynchronize();
     if (plan->d_table) (void)hipFree(plan->d_table);
-    if (plan->d_ws) (void)hipFree(plan->d_ws);
     delete plan;
     return e == hipSuccess ? DPD_OK : hip_fail(e);
 }

@@ -14,7 +14,6 @@ struct dpd_plan {
     dpd_tune tune;
     std::vector<float> raw;      // host copy of the 2K coefficient floats
     float *d_table = nullptr;    // precombined table (device)
-    void *d_ws = nullptr;        // reserved
 };
 
 namespace dpd {
