@@ -241,8 +241,9 @@ __device__ __forceinline__ void wave_lds_order()
 //   * the next chunk is already in flight (register prefetch); every
 //     load instruction is a nontemporal read of 1 KiB of contiguous memory
 //     (lane l, part i -> the 16 bytes at sample 2*(l + 64 i)); the L-1 halo
-//     samples before the chunk come through the scalar cache (zeros at a row
-//     start, the caller's history before row 0);
+//     samples before the chunk are read by the first L-1 lanes, one each (a
+//     vector load, in order with the chunk's; zeros at a row start, the
+//     caller's history before row 0);
 //   * samples and |x|^2 go to a wave-private LDS buffer laid out with one pad
 //     slot after every S samples (odd lane stride: conflict-free window reads);
 //     each lane reads its S+L-1 consecutive-sample window back, filters and
@@ -316,9 +317,9 @@ __global__ void __launch_bounds__(kBlock) fwd_stream_kernel(FwdParams p)
     float2 hist_v = make_float2(0.f, 0.f);
     if (HS > 0 && p.hist != nullptr) hist_v = p.hist[hl];
 
-    // raw sample for halo sample hl - HS of the chunk starting at t0: the HS
-    // samples sit at a uniform address, so they come through the scalar cache.
-    // At a row start (t0 < HS) nothing is read; the value is replaced at use.
+    // raw sample for halo sample hl - HS of the chunk starting at t0 (lane hl
+    // selects its own sample; the compiler makes it one per-lane load).  At a
+    // row start (t0 < HS) nothing is read; the value is replaced at use.
     auto halo_raw = [&](int64_t row, int64_t t0) {
         float2 r = make_float2(0.f, 0.f);
         if (HS > 0 && t0 >= HS) {
