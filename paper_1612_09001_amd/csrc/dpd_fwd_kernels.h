@@ -69,15 +69,30 @@ __device__ __forceinline__ void fir_outputs(const float (&a)[S + L - 1], const f
                                             const float (&s)[S + L - 1], const float (&top)[4 * L],
                                             const cfloat *M, float (&zr)[S], float (&zi)[S])
 {
-    const float cr = M[4 * L * NI], ci = M[4 * L * NI + 1];
+    constexpr int T = 4 * (NI - 1);   // scalar coefficients per tap
+    // An opaque zero offset keeps the scalar loads inside the caller's chunk
+    // loop: hoisted, the whole table would not fit the scalar registers and
+    // would be spilled to VGPR lanes and read back with one v_readlane each.
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    const cfloat *Mz = M + z;
+    const float cr = Mz[4 * L * NI], ci = Mz[4 * L * NI + 1];
 #pragma unroll
     for (int i = 0; i < S; ++i) {
         zr[i] = cr;
         zi[i] = ci;
     }
+    // tap k's coefficients are in c while tap k + 1's load
+    float c[T > 0 ? T : 1];
+#pragma unroll
+    for (int e = 0; e < T; ++e) c[e] = Mz[e];
 #pragma unroll
     for (int k = 0; k < L; ++k) {
-        const cfloat *Mk = M + 4 * NI * k;
+        float cn[T > 0 ? T : 1];
+        if (k + 1 < L) {
+#pragma unroll
+            for (int e = 0; e < T; ++e) cn[e] = Mz[4 * NI * (k + 1) + e];
+        }
 #pragma unroll
         for (int i = 0; i < S; ++i) {
             const int w = i + (L - 1) - k;
@@ -85,15 +100,19 @@ __device__ __forceinline__ void fir_outputs(const float (&a)[S + L - 1], const f
             float w10 = top[4 * k + 2], w11 = top[4 * k + 3];
 #pragma unroll
             for (int j = NI - 2; j >= 0; --j) {
-                w00 = __builtin_fmaf(w00, s[w], Mk[4 * j + 0]);
-                w01 = __builtin_fmaf(w01, s[w], Mk[4 * j + 1]);
-                w10 = __builtin_fmaf(w10, s[w], Mk[4 * j + 2]);
-                w11 = __builtin_fmaf(w11, s[w], Mk[4 * j + 3]);
+                w00 = __builtin_fmaf(w00, s[w], c[4 * j + 0]);
+                w01 = __builtin_fmaf(w01, s[w], c[4 * j + 1]);
+                w10 = __builtin_fmaf(w10, s[w], c[4 * j + 2]);
+                w11 = __builtin_fmaf(w11, s[w], c[4 * j + 3]);
             }
             zr[i] = __builtin_fmaf(w00, a[w], zr[i]);
             zr[i] = __builtin_fmaf(w01, b[w], zr[i]);
             zi[i] = __builtin_fmaf(w10, a[w], zi[i]);
             zi[i] = __builtin_fmaf(w11, b[w], zi[i]);
+        }
+        if (k + 1 < L) {
+#pragma unroll
+            for (int e = 0; e < T; ++e) c[e] = cn[e];
         }
     }
 }
