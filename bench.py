@@ -93,11 +93,35 @@ def cpu_baseline(x_host, z_gpu, mo, co, L, h):
     n = x_host.size
     acc = {"nmse_db": round(nmse_db(z_gpu, z), 2), "max_rel": float("%.3g" % max_rel(z_gpu, z))}
     acc["pass"] = bool(acc["nmse_db"] <= -110.0 and acc["max_rel"] <= 2e-5)
-    base = {"value": round(n / t / 1e6, 3), "unit": "Msamples/s", "cores": orc.threads(),
+    threads = orc.threads()
+    # the same oracle on one thread, over the first 2^21 samples
+    m = min(n, 1 << 21)
+    orc.set_threads(1)
+    t1 = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        orc.forward(x_host[:m], mo, co, L, h)
+        t1.append(time.perf_counter() - t0)
+    orc.set_threads(threads)
+    base = {"value": round(n / t / 1e6, 3), "unit": "Msamples/s", "cores": threads,
             "kind": "oracle",
             "sample": "whole headline workload: %d samples through the FP64 C oracle "
-                      "(gcc -O2, OpenMP), median of 3" % n}
+                      "(gcc -O2, OpenMP), median of 3" % n,
+            "single_thread_value": round(m / float(np.median(t1)) / 1e6, 3),
+            "single_thread_sample": "first %d samples of the same workload, one thread, median of 3" % m,
+            "cpu_model": _cpu_model()}
     return base, acc
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _rotating(torch, x_host, total_bytes=ROTATE_BYTES):

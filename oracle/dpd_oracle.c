@@ -57,6 +57,17 @@ int oracle_threads(void)
 #endif
 }
 
+/* Threads of the following calls (n >= 1); the timing of the CPU baseline at
+   one thread uses it. */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 static int check_orders(const int32_t *orders, int32_t n)
 {
     if (n < 0) return 0;

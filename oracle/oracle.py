@@ -38,6 +38,8 @@ _f64p = ctypes.c_void_p
 
 def _declare(lib):
     lib.oracle_threads.restype = ctypes.c_int
+    lib.oracle_set_threads.restype = None
+    lib.oracle_set_threads.argtypes = [ctypes.c_int]
     lib.oracle_forward.restype = ctypes.c_int
     lib.oracle_forward.argtypes = [_f64p, ctypes.c_int64, _f64p, _i32p, ctypes.c_int32, _i32p,
                                    ctypes.c_int32, ctypes.c_int32, _f64p, _f64p]
@@ -82,6 +84,10 @@ class Oracle:
 
     def threads(self) -> int:
         return int(self.lib.oracle_threads())
+
+    def set_threads(self, n: int):
+        """OpenMP threads of the following calls."""
+        self.lib.oracle_set_threads(int(n))
 
     def forward(self, x, main_orders, conj_orders, L, coeffs, hist=None) -> np.ndarray:
         x = _c128(x)
