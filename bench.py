@@ -557,6 +557,11 @@ def main():
         dpd.dpd_apply(handle, stream, ptrs[i % nbuf][0], ptrs[i % nbuf][1], n)
     plan.set_tune(samples_per_thread=tune["samples_per_thread"], stage_lds=tune["stage_lds"],
                   grid_mult=tune["grid_mult"])
+    # a plain device copy of the same bytes over the same buffers through the
+    # runtime (torch copy_ = hipMemcpyAsync), on warm clocks (the timed launches
+    # then rewrite every output)
+    _, copy_ms = _time_launches(torch, lambda i: zs[i].copy_(xs[i]), nbuf, min(args.steps, 200), 20)
+    copy_gbs = BYTES_PER_SAMPLE * n / (copy_ms * 1e-3) / 1e9
     wall, kern_ms = _time_launches(
         torch, lambda i: dpd.dpd_apply(handle, stream, ptrs[i][0], ptrs[i][1], n), nbuf,
         args.steps, 1)
@@ -584,7 +589,9 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_from_profile(n),
                      "kernel_ms": round(kern_ms, 5),
-                     "algorithmic_bytes_per_launch": BYTES_PER_SAMPLE * n},
+                     "algorithmic_bytes_per_launch": BYTES_PER_SAMPLE * n,
+                     "runtime_copy_gbs": round(copy_gbs, 1),
+                     "frac_of_runtime_copy": round(achieved / copy_gbs, 4)},
     }
     z_last = zs[(args.steps - 1) % nbuf]
     if not args.main_only:
