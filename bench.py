@@ -454,7 +454,10 @@ def leg_ls(torch, dpd, signals, reps=5):
 
 def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
     """64 x 2^18 samples, DPD orders {1,3,5,7} both branches, L = 6, identity
-    start, synthetic PA, loss mean|y/10 - x|^2, Adam lr 1e-3."""
+    start, synthetic PA, loss mean|y/10 - x|^2, Adam lr 1e-3: the fused step
+    (transmitter and loss in one kernel, its adjoint in another), the same
+    step with the transmitter as separate launches per stage, autograd over
+    DPDFunction nodes and plain-ops autograd."""
     from paper_1612_09001_amd.baselines import PlainTrainer
     from paper_1612_09001_amd.train import AutogradTrainer, FusedTrainer
 
@@ -478,6 +481,7 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
         return ms, [float(v.item()) for v in losses]
 
     fused_ms, fused_loss = run(FusedTrainer(xd, orders, orders, L, h0), steps)
+    stage_ms, stage_loss = run(FusedTrainer(xd, orders, orders, L, h0, fused_transmitter=False), 50)
     auto_ms, auto_loss = run(AutogradTrainer(xd, orders, orders, L, h0), plain_steps)
     plain_ms, plain_loss = run(PlainTrainer(xd, orders, orders, L, h0), plain_steps)
     k = min(plain_steps, steps)
@@ -486,6 +490,9 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
     med = lambda v: float(np.median(v[10:] if len(v) > 12 else v[2:]))
     return {"workload": "64x2^18 OFDM-like, DPD {1,3,5,7} main+conj L=6, synthetic PA, Adam 1e-3",
             "grad_step_ms_fused": round(med(fused_ms), 4),
+            "grad_step_ms_fused_transmitter_per_stage": round(med(stage_ms), 4),
+            "per_stage_vs_fused_loss_rel_max_first_50": float("%.3g" % float(np.max(
+                np.abs(np.array(stage_loss) - np.array(fused_loss[:50])) / np.array(fused_loss[:50])))),
             "grad_step_ms_autograd_dpdfunction": round(med(auto_ms), 4),
             "grad_step_ms_plain_ops_autograd": round(med(plain_ms), 4),
             "speedup_vs_plain_ops": round(med(plain_ms) / med(fused_ms), 2),

@@ -217,6 +217,29 @@ dpd_status dpd_loss_grad(void *stream, const void *y, const void *x, int64_t n, 
 dpd_status dpd_adam_step(void *stream, float *params, const float *grads, float *m, float *v,
                          int64_t count, int32_t step, float lr, float beta1, float beta2, float eps);
 
+/* dpd_cascade_loss_grad -- the transmitter model of the learning loop as two
+ * APH stages (Eq. 1 each) fused with the loss: per row, u = A(z) with A a
+ * memoryless plan (L == 1: I/Q imbalance, LO leakage, static nonlinearity)
+ * and y = B(u) with B a plan with memory (a PA), u taken as zero before the
+ * row start; then E = (1/(rows n)) sum |scale*y - x|^2 into *loss_dev and
+ * dE/dy = (2 scale / (rows n)) (scale*y - x) into grad_y, as dpd_loss_grad
+ * computes from y.  u and y are never stored.  z, x, grad_y: device
+ * complex64, rows x n at stride ld samples (ld >= n; ignored when rows == 1),
+ * 8-byte aligned; grad_y must not overlap z or x.  ws: >= dpd_loss_ws_size
+ * bytes.  DPD_EINVAL if A has more than one tap; DPD_EUNSUPPORTED if B has
+ * orders above 7 or more than 4 taps (run the stages with dpd_apply_rows and
+ * dpd_loss_grad instead).  Deterministic; allocates nothing.
+ *
+ * dpd_cascade_backward -- dE/dz from dE/dy through the same cascade: the
+ * adjoint of B at u = A(z) (recomputed), then the adjoint of A, in the
+ * complex-gradient convention of dpd_backward.  grad_z must not overlap z or
+ * grad_y.  Same layout and limits. */
+dpd_status dpd_cascade_loss_grad(const dpd_plan *A, const dpd_plan *B, void *stream, const void *z,
+                                 const void *x, int64_t rows, int64_t n, int64_t ld, float scale,
+                                 float *loss_dev, void *grad_y, void *ws, size_t ws_bytes);
+dpd_status dpd_cascade_backward(const dpd_plan *A, const dpd_plan *B, void *stream, const void *z,
+                                const void *grad_y, void *grad_z, int64_t rows, int64_t n, int64_t ld);
+
 /* ------------------------------------------------------- least squares --
  * The paper's coefficient estimate (section 2.2, Eq. 2): with the plan's
  * basis, row m of Psi is

@@ -84,6 +84,419 @@ __global__ void __launch_bounds__(kBlock) adam_kernel(float *__restrict__ p, con
 
 using namespace dpd;
 
+namespace dpd {
+
+// ----------------------------------------------------------- cascade ---
+// A transmitter model of two APH stages, u = A(z) with A memoryless (one tap:
+// I/Q imbalance, LO leakage, static nonlinearity) and y = B(u) (a PA with
+// memory), fused with the loss above.  One thread takes four consecutive
+// samples of a row; the L_B - 1 values of u before them are recomputed from
+// z (memoryless A), read from the neighbouring threads' cache lines, so u is
+// never stored.  Stage B sees zero input before each row start.
+
+constexpr int kCasQ = 4;   // samples per thread
+
+struct CasParams {
+    const float *A;          // precombined table of stage A (L = 1)
+    const float *B;          // precombined table of stage B
+    int NIA;                 // power levels of A
+    const float2 *z, *x;     // rows x n at stride ld
+    const float2 *gy;        // backward: dE/dy
+    float2 *out;             // forward: dE/dy; backward: dE/dz
+    int64_t rows, n, ld, qpr;   // qpr = ceil(n / 4) quads per row
+    float scale, gscale;
+    float *partials;         // forward: one loss partial per block
+    int vec;                 // rows start 16-byte aligned: whole quads use 16-byte accesses
+};
+
+constexpr int kCasTA = 4 * kMaxNI + 2;   // stage-A table floats held in registers (at most)
+
+// A(z) for one sample (memoryless: c + W(|z|^2) z, W by Horner over NIA levels)
+__device__ __forceinline__ float2 cas_stage_a(const float (&T)[kCasTA], int NIA, float2 v)
+{
+    const float s = __builtin_fmaf(v.x, v.x, v.y * v.y);
+    float w00 = 0.f, w01 = 0.f, w10 = 0.f, w11 = 0.f, cr = 0.f, ci = 0.f;
+#pragma unroll
+    for (int j = kMaxNI - 1; j >= 0; --j) {
+        if (j < NIA) {
+            w00 = __builtin_fmaf(w00, s, T[4 * j + 0]);
+            w01 = __builtin_fmaf(w01, s, T[4 * j + 1]);
+            w10 = __builtin_fmaf(w10, s, T[4 * j + 2]);
+            w11 = __builtin_fmaf(w11, s, T[4 * j + 3]);
+        }
+        if (j == NIA) {
+            cr = T[4 * j];
+            ci = T[4 * j + 1];
+        }
+    }
+    if (NIA == kMaxNI) {
+        cr = T[4 * kMaxNI];
+        ci = T[4 * kMaxNI + 1];
+    }
+    return make_float2(__builtin_fmaf(w00, v.x, __builtin_fmaf(w01, v.y, cr)),
+                       __builtin_fmaf(w10, v.x, __builtin_fmaf(w11, v.y, ci)));
+}
+
+// Adjoint sum of one sample at input v from U_j = sum_k M_{j,k}^T g_{m+k}:
+// P + 2 Q v with P = sum_j s^j U_j, Q = sum_j j s^(j-1) (v . U_j), both by
+// Horner from the top level down.
+template <int NI>
+__device__ __forceinline__ float2 cas_adjoint_sum(const float (&Ux)[NI], const float (&Uy)[NI], float2 v)
+{
+    const float s = __builtin_fmaf(v.x, v.x, v.y * v.y);
+    float px = Ux[NI - 1], py = Uy[NI - 1], q = 0.f;
+#pragma unroll
+    for (int j = NI - 1; j >= 1; --j) {
+        q = __builtin_fmaf(q, s, (float)j * __builtin_fmaf(v.x, Ux[j], v.y * Uy[j]));
+        px = __builtin_fmaf(px, s, Ux[j - 1]);
+        py = __builtin_fmaf(py, s, Uy[j - 1]);
+    }
+    return make_float2(__builtin_fmaf(2.f * q, v.x, px), __builtin_fmaf(2.f * q, v.y, py));
+}
+
+__device__ __forceinline__ float2 cas_load(const float2 *__restrict__ r, int64_t m, int64_t n)
+{
+    return (m >= 0 && m < n) ? r[m] : make_float2(0.f, 0.f);
+}
+
+// Both tables into registers, once per thread.
+template <int NIB, int LB>
+__device__ __forceinline__ void cas_tables(const CasParams &p, float (&ta)[kCasTA], float (&tb)[4 * LB * NIB + 2])
+{
+#pragma unroll
+    for (int e = 0; e < kCasTA; ++e) ta[e] = e < 4 * p.NIA + 2 ? p.A[e] : 0.f;
+#pragma unroll
+    for (int e = 0; e < 4 * LB * NIB + 2; ++e) tb[e] = p.B[e];
+}
+
+// This thread's quads: (row, quad) starting at q0 and advanced by the grid
+// stride without a division.
+struct CasWalk {
+    int64_t row, k, dr, dk;
+    __device__ CasWalk(int64_t q0, int64_t stride, int64_t qpr)
+        : row(q0 / qpr), k(q0 - (q0 / qpr) * qpr), dr(stride / qpr), dk(stride - (stride / qpr) * qpr) {}
+    __device__ void next(int64_t qpr)
+    {
+        row += dr;
+        k += dk;
+        if (k >= qpr) {
+            k -= qpr;
+            ++row;
+        }
+    }
+};
+
+// Forward: E partials and dE/dy.
+template <int NIB, int LB>
+__global__ void __launch_bounds__(kBlock) cascade_fwd_kernel(CasParams p)
+{
+    constexpr int W = kCasQ + LB - 1;
+    __shared__ float red[kBlock];
+    float ta[kCasTA], tb[4 * LB * NIB + 2];
+    cas_tables<NIB, LB>(p, ta, tb);
+    float acc = 0.f;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t q0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    CasWalk wk(q0, stride, p.qpr);
+    for (; wk.row < p.rows; wk.next(p.qpr)) {
+        const int64_t m0 = wk.k * kCasQ;
+        const float2 *zr = p.z + wk.row * p.ld;
+        const float2 *xr = p.x + wk.row * p.ld;
+        float2 *gr = p.out + wk.row * p.ld;
+        // z over the window m0 - (LB-1) .. m0 + 3; 16-byte loads inside the row
+        const bool vec = p.vec && m0 + kCasQ <= p.n;
+        float2 zw[W], xv[kCasQ];
+        if (vec) {
+            const float4 a0 = reinterpret_cast<const float4 *>(zr + m0)[0];
+            const float4 a1 = reinterpret_cast<const float4 *>(zr + m0)[1];
+            zw[LB - 1] = make_float2(a0.x, a0.y);
+            zw[LB] = make_float2(a0.z, a0.w);
+            zw[LB + 1] = make_float2(a1.x, a1.y);
+            zw[LB + 2] = make_float2(a1.z, a1.w);
+            const float4 b0 = reinterpret_cast<const float4 *>(xr + m0)[0];
+            const float4 b1 = reinterpret_cast<const float4 *>(xr + m0)[1];
+            xv[0] = make_float2(b0.x, b0.y);
+            xv[1] = make_float2(b0.z, b0.w);
+            xv[2] = make_float2(b1.x, b1.y);
+            xv[3] = make_float2(b1.z, b1.w);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kCasQ; ++i) {
+                zw[LB - 1 + i] = cas_load(zr, m0 + i, p.n);
+                xv[i] = cas_load(xr, m0 + i, p.n);
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < LB - 1; ++w) zw[w] = cas_load(zr, m0 - (LB - 1) + w, p.n);
+        // u = A(z); zero before the row start (stage B's zero history) and past its end
+        float2 u[W];
+        float sw[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int64_t m = m0 - (LB - 1) + w;
+            u[w] = (m >= 0 && m < p.n) ? cas_stage_a(ta, p.NIA, zw[w]) : make_float2(0.f, 0.f);
+            sw[w] = __builtin_fmaf(u[w].x, u[w].x, u[w].y * u[w].y);
+        }
+        float2 g[kCasQ];
+#pragma unroll
+        for (int i = 0; i < kCasQ; ++i) {
+            float yr = tb[4 * LB * NIB], yi = tb[4 * LB * NIB + 1];
+#pragma unroll
+            for (int k = 0; k < LB; ++k) {
+                const int w = i + (LB - 1) - k;
+                const float *t = tb + 4 * NIB * k;
+                float w00 = t[4 * (NIB - 1)], w01 = t[4 * (NIB - 1) + 1];
+                float w10 = t[4 * (NIB - 1) + 2], w11 = t[4 * (NIB - 1) + 3];
+#pragma unroll
+                for (int j = NIB - 2; j >= 0; --j) {
+                    w00 = __builtin_fmaf(w00, sw[w], t[4 * j + 0]);
+                    w01 = __builtin_fmaf(w01, sw[w], t[4 * j + 1]);
+                    w10 = __builtin_fmaf(w10, sw[w], t[4 * j + 2]);
+                    w11 = __builtin_fmaf(w11, sw[w], t[4 * j + 3]);
+                }
+                yr = __builtin_fmaf(w00, u[w].x, __builtin_fmaf(w01, u[w].y, yr));
+                yi = __builtin_fmaf(w10, u[w].x, __builtin_fmaf(w11, u[w].y, yi));
+            }
+            const bool in = m0 + i < p.n;
+            const float rr = in ? __builtin_fmaf(p.scale, yr, -xv[i].x) : 0.f;
+            const float ri = in ? __builtin_fmaf(p.scale, yi, -xv[i].y) : 0.f;
+            acc = __builtin_fmaf(rr, rr, __builtin_fmaf(ri, ri, acc));
+            g[i] = make_float2(p.gscale * rr, p.gscale * ri);
+        }
+        if (vec) {
+            reinterpret_cast<float4 *>(gr + m0)[0] = make_float4(g[0].x, g[0].y, g[1].x, g[1].y);
+            reinterpret_cast<float4 *>(gr + m0)[1] = make_float4(g[2].x, g[2].y, g[3].x, g[3].y);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kCasQ; ++i)
+                if (m0 + i < p.n) gr[m0 + i] = g[i];
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) p.partials[blockIdx.x] = red[0];
+}
+
+// Backward: dE/dz = A'(z)^T B'(u)^T dE/dy with u = A(z) recomputed.
+template <int NIB, int LB>
+__global__ void __launch_bounds__(kBlock) cascade_bwd_kernel(CasParams p)
+{
+    constexpr int W = kCasQ + LB - 1;
+    float ta[kCasTA], tb[4 * LB * NIB + 2];
+    cas_tables<NIB, LB>(p, ta, tb);
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t q0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    CasWalk wk(q0, stride, p.qpr);
+    for (; wk.row < p.rows; wk.next(p.qpr)) {
+        const int64_t m0 = wk.k * kCasQ;
+        const float2 *zr = p.z + wk.row * p.ld;
+        const float2 *gyr = p.gy + wk.row * p.ld;
+        float2 *out = p.out + wk.row * p.ld;
+        const bool vec = p.vec && m0 + kCasQ <= p.n;
+        float2 zv[kCasQ], g[W];   // g: dE/dy at m0 .. m0 + 3 + LB - 1 (zero past the row end)
+        if (vec) {
+            const float4 a0 = reinterpret_cast<const float4 *>(zr + m0)[0];
+            const float4 a1 = reinterpret_cast<const float4 *>(zr + m0)[1];
+            zv[0] = make_float2(a0.x, a0.y);
+            zv[1] = make_float2(a0.z, a0.w);
+            zv[2] = make_float2(a1.x, a1.y);
+            zv[3] = make_float2(a1.z, a1.w);
+            const float4 b0 = reinterpret_cast<const float4 *>(gyr + m0)[0];
+            const float4 b1 = reinterpret_cast<const float4 *>(gyr + m0)[1];
+            g[0] = make_float2(b0.x, b0.y);
+            g[1] = make_float2(b0.z, b0.w);
+            g[2] = make_float2(b1.x, b1.y);
+            g[3] = make_float2(b1.z, b1.w);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kCasQ; ++i) {
+                zv[i] = cas_load(zr, m0 + i, p.n);
+                g[i] = cas_load(gyr, m0 + i, p.n);
+            }
+        }
+#pragma unroll
+        for (int w = kCasQ; w < W; ++w) g[w] = cas_load(gyr, m0 + w, p.n);
+        float2 res[kCasQ];
+#pragma unroll
+        for (int i = 0; i < kCasQ; ++i) {
+            const float2 uv = cas_stage_a(ta, p.NIA, zv[i]);
+            // adjoint of B at u_m: U_j = sum_k M_{j,k}^T g_{m+k}
+            float Ux[NIB], Uy[NIB];
+#pragma unroll
+            for (int j = 0; j < NIB; ++j) {
+                float ax = 0.f, ay = 0.f;
+#pragma unroll
+                for (int k = 0; k < LB; ++k) {
+                    const float *t = tb + 4 * (k * NIB + j);
+                    ax = __builtin_fmaf(t[0], g[i + k].x, __builtin_fmaf(t[2], g[i + k].y, ax));
+                    ay = __builtin_fmaf(t[1], g[i + k].x, __builtin_fmaf(t[3], g[i + k].y, ay));
+                }
+                Ux[j] = ax;
+                Uy[j] = ay;
+            }
+            const float2 gu = cas_adjoint_sum<NIB>(Ux, Uy, uv);
+            // adjoint of A at z_m (one tap, NIA levels): V_j = M_j^T gu, the
+            // same P + 2 Q v by Horner from the top level down
+            const float2 z1 = zv[i];
+            const float sa = __builtin_fmaf(z1.x, z1.x, z1.y * z1.y);
+            float px = 0.f, py = 0.f, qa = 0.f;
+#pragma unroll
+            for (int j = kMaxNI - 1; j >= 0; --j) {
+                if (j < p.NIA) {
+                    const float vx = __builtin_fmaf(ta[4 * j + 0], gu.x, ta[4 * j + 2] * gu.y);
+                    const float vy = __builtin_fmaf(ta[4 * j + 1], gu.x, ta[4 * j + 3] * gu.y);
+                    px = __builtin_fmaf(px, sa, vx);
+                    py = __builtin_fmaf(py, sa, vy);
+                    if (j >= 1) qa = __builtin_fmaf(qa, sa, (float)j * __builtin_fmaf(z1.x, vx, z1.y * vy));
+                }
+            }
+            res[i] = make_float2(__builtin_fmaf(2.f * qa, z1.x, px), __builtin_fmaf(2.f * qa, z1.y, py));
+        }
+        if (vec) {
+            reinterpret_cast<float4 *>(out + m0)[0] = make_float4(res[0].x, res[0].y, res[1].x, res[1].y);
+            reinterpret_cast<float4 *>(out + m0)[1] = make_float4(res[2].x, res[2].y, res[3].x, res[3].y);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kCasQ; ++i)
+                if (m0 + i < p.n) out[m0 + i] = res[i];
+        }
+    }
+}
+
+constexpr int kCasMaxNI = 4;   // stage B: orders up to 7
+constexpr int kCasMaxL = 4;    // stage B: up to 4 taps
+
+typedef void (*CasKernel)(CasParams);
+
+template <int NI, int L>
+struct CasEntry {
+    static void fill(CasKernel (&f)[kCasMaxNI][kCasMaxL], CasKernel (&b)[kCasMaxNI][kCasMaxL])
+    {
+        f[NI - 1][L - 1] = &cascade_fwd_kernel<NI, L>;
+        b[NI - 1][L - 1] = &cascade_bwd_kernel<NI, L>;
+        if constexpr (L < kCasMaxL)
+            CasEntry<NI, L + 1>::fill(f, b);
+        else if constexpr (NI < kCasMaxNI)
+            CasEntry<NI + 1, 1>::fill(f, b);
+    }
+};
+
+struct CasTable {
+    CasKernel fwd[kCasMaxNI][kCasMaxL];
+    CasKernel bwd[kCasMaxNI][kCasMaxL];
+    CasTable() { CasEntry<1, 1>::fill(fwd, bwd); }
+};
+
+static const CasTable &cas_table()
+{
+    static const CasTable t;
+    return t;
+}
+
+static dpd_status cas_check(const dpd_plan *A, const dpd_plan *B, const void *p0, const void *p1, const void *out,
+                            int64_t rows, int64_t n, int64_t ld)
+{
+    if (A == nullptr || B == nullptr) return DPD_EINVAL;
+    if (A->map.L != 1) return DPD_EINVAL;
+    if (B->map.NI > kCasMaxNI || B->map.L > kCasMaxL) return DPD_EUNSUPPORTED;
+    if (rows < 0 || n < 0 || (rows > 1 && ld < n)) return DPD_EINVAL;
+    if (rows == 0 || n == 0) return DPD_OK;
+    if (p0 == nullptr || p1 == nullptr || out == nullptr) return DPD_EINVAL;
+    for (const void *q : {p0, p1, out})
+        if ((uintptr_t)q % 8 != 0) return DPD_EINVAL;
+    const size_t span = (size_t)(((rows - 1) * (rows > 1 ? ld : n) + n) * (int64_t)sizeof(float2));
+    const auto lap = [&](const void *a, const void *b) {
+        const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+        return x < y + span && y < x + span;
+    };
+    if (lap(out, p0) || lap(out, p1)) return DPD_EINVAL;
+    return DPD_OK;
+}
+
+static int cas_grid(int64_t total)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>(kLossBlocks, (total + kBlock - 1) / kBlock));
+}
+
+}  // namespace dpd
+
+using namespace dpd;
+
+DPD_EXPORT dpd_status dpd_cascade_loss_grad(const dpd_plan *A, const dpd_plan *B, void *stream, const void *z,
+                                            const void *x, int64_t rows, int64_t n, int64_t ld, float scale,
+                                            float *loss_dev, void *grad_y, void *ws, size_t ws_bytes)
+{
+    dpd_status st = cas_check(A, B, z, x, grad_y, rows, n, ld);
+    if (st != DPD_OK) return st;
+    if (ws == nullptr || ws_bytes < kLossBlocks * sizeof(float) || (uintptr_t)ws % 4 != 0) return DPD_EINVAL;
+    if (!std::isfinite(scale)) return DPD_EINVAL;
+    const hipStream_t hs = (hipStream_t)stream;
+    const int64_t N = rows * n;
+    int nblk = 0;
+    if (N > 0) {
+        CasParams p;
+        p.A = A->d_table;
+        p.B = B->d_table;
+        p.NIA = A->map.NI;
+        p.z = (const float2 *)z;
+        p.x = (const float2 *)x;
+        p.gy = nullptr;
+        p.out = (float2 *)grad_y;
+        p.rows = rows;
+        p.n = n;
+        p.ld = rows > 1 ? ld : n;
+        p.qpr = (n + kCasQ - 1) / kCasQ;
+        p.scale = scale;
+        p.gscale = (float)(2.0 * scale / (double)N);
+        p.partials = (float *)ws;
+        p.vec = ((uintptr_t)z % 16 == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)grad_y % 16 == 0 &&
+                 (rows == 1 || ld % 2 == 0)) ? 1 : 0;
+        nblk = cas_grid(rows * p.qpr);
+        hipLaunchKernelGGL(cas_table().fwd[B->map.NI - 1][B->map.L - 1], dim3(nblk), dim3(kBlock), 0, hs, p);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    if (loss_dev != nullptr) {
+        hipLaunchKernelGGL(loss_finalize, dim3(1), dim3(kBlock), 0, hs, (const float *)ws, nblk,
+                           N > 0 ? 1.0 / (double)N : 0.0, loss_dev);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    return DPD_OK;
+}
+
+DPD_EXPORT dpd_status dpd_cascade_backward(const dpd_plan *A, const dpd_plan *B, void *stream, const void *z,
+                                           const void *grad_y, void *grad_z, int64_t rows, int64_t n, int64_t ld)
+{
+    dpd_status st = cas_check(A, B, z, grad_y, grad_z, rows, n, ld);
+    if (st != DPD_OK || rows == 0 || n == 0) return st;
+    CasParams p;
+    p.A = A->d_table;
+    p.B = B->d_table;
+    p.NIA = A->map.NI;
+    p.z = (const float2 *)z;
+    p.x = nullptr;
+    p.gy = (const float2 *)grad_y;
+    p.out = (float2 *)grad_z;
+    p.rows = rows;
+    p.n = n;
+    p.ld = rows > 1 ? ld : n;
+    p.qpr = (n + kCasQ - 1) / kCasQ;
+    p.scale = 0.f;
+    p.gscale = 0.f;
+    p.partials = nullptr;
+    p.vec = ((uintptr_t)z % 16 == 0 && (uintptr_t)grad_y % 16 == 0 && (uintptr_t)grad_z % 16 == 0 &&
+             (rows == 1 || ld % 2 == 0)) ? 1 : 0;
+    hipLaunchKernelGGL(cas_table().bwd[B->map.NI - 1][B->map.L - 1], dim3(cas_grid(rows * p.qpr)), dim3(kBlock), 0,
+                       (hipStream_t)stream, p);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DPD_OK : hip_fail(e);
+}
+
 DPD_EXPORT dpd_status dpd_loss_ws_size(int64_t n, size_t *bytes)
 {
     if (n < 0 || bytes == nullptr) return DPD_EINVAL;

@@ -4,11 +4,16 @@
 kernels, on buffers allocated once:
 
   z = DPD(x)                 forward, coefficients read from the device
-  u = IQ(z), y = PA(u)       the synthetic transmitter (pa.py)
-  E, dE/dy                   loss E = mean |y/G - x|^2 and its gradient
-  dE/du, dE/dz               adjoint of PA and IQ (input gradients only)
+  E, dE/dy                   the synthetic transmitter u = IQ(z), y = PA(u)
+                             (pa.py) fused with the loss E = mean |y/G - x|^2
+                             and its gradient (dpd_cascade_loss_grad: u and y
+                             are never stored)
+  dE/dz                      adjoint of PA and IQ (dpd_cascade_backward)
   dE/dcoeffs                 adjoint of the predistorter (coefficients only)
   Adam                       update of the K complex coefficients
+
+``fused_transmitter=False`` runs the transmitter and its adjoint as separate
+launches per stage (IQ, PA, loss; PA and IQ adjoints) instead.
 
 ``AutogradTrainer`` is the same step through ``torch.autograd`` with the
 predistorter and both PA stages as ``DPDFunction`` nodes (hand-written
@@ -26,7 +31,7 @@ from .pa import SyntheticPA, iq_coeffs, pa_coeffs
 
 class FusedTrainer:
     def __init__(self, x, main_orders, conj_orders, L, coeffs0, lr=1e-3, betas=(0.9, 0.999),
-                 eps=1e-8):
+                 eps=1e-8, fused_transmitter=True):
         if x.dim() != 2 or not x.is_contiguous():
             raise ValueError("x must be a contiguous (rows, n) complex64 GPU tensor")
         self.x = x
@@ -36,12 +41,14 @@ class FusedTrainer:
         dev = x.device
         self.coeffs = torch.as_tensor(np.asarray(coeffs0, dtype=np.complex64)).to(dev).contiguous()
         self.pa = SyntheticPA()
+        self.fused_transmitter = bool(fused_transmitter)
         self.z = torch.empty_like(x)
-        self.u = torch.empty_like(x)
-        self.y = torch.empty_like(x)
         self.gy = torch.empty_like(x)
-        self.gu = torch.empty_like(x)
         self.gz = torch.empty_like(x)
+        if not self.fused_transmitter:
+            self.u = torch.empty_like(x)
+            self.y = torch.empty_like(x)
+            self.gu = torch.empty_like(x)
         self.gc = torch.empty(self.K, dtype=torch.complex64, device=dev)
         self.m = torch.zeros(2 * self.K, dtype=torch.float32, device=dev)
         self.v = torch.zeros(2 * self.K, dtype=torch.float32, device=dev)
@@ -60,14 +67,20 @@ class FusedTrainer:
         R, N, ld = self.rows, self.n, self.n
         P = lambda t: t.data_ptr()
         _dpd.dpd_apply_coeffs(self.plan.handle, st, P(self.coeffs), P(self.x), P(self.z), R, N, ld)
-        _dpd.dpd_apply_rows(self.pa.iq.handle, st, P(self.z), P(self.u), R, N, ld)
-        _dpd.dpd_apply_rows(self.pa.pa.handle, st, P(self.u), P(self.y), R, N, ld)
-        _dpd.dpd_loss_grad(st, P(self.y), P(self.x), R * N, 1.0 / self.pa.gain, P(self.loss),
-                           P(self.gy), P(self.ws), self.ws_bytes)
-        _dpd.dpd_backward(self.pa.pa.handle, st, 0, P(self.u), P(self.gy), P(self.gu), 0, R, N, ld,
-                          P(self.ws), self.ws_bytes)
-        _dpd.dpd_backward(self.pa.iq.handle, st, 0, P(self.z), P(self.gu), P(self.gz), 0, R, N, ld,
-                          P(self.ws), self.ws_bytes)
+        iq, pa = self.pa.iq.handle, self.pa.pa.handle
+        if self.fused_transmitter:
+            _dpd.dpd_cascade_loss_grad(iq, pa, st, P(self.z), P(self.x), R, N, ld, 1.0 / self.pa.gain,
+                                       P(self.loss), P(self.gy), P(self.ws), self.ws_bytes)
+            _dpd.dpd_cascade_backward(iq, pa, st, P(self.z), P(self.gy), P(self.gz), R, N, ld)
+        else:
+            _dpd.dpd_apply_rows(iq, st, P(self.z), P(self.u), R, N, ld)
+            _dpd.dpd_apply_rows(pa, st, P(self.u), P(self.y), R, N, ld)
+            _dpd.dpd_loss_grad(st, P(self.y), P(self.x), R * N, 1.0 / self.pa.gain, P(self.loss),
+                               P(self.gy), P(self.ws), self.ws_bytes)
+            _dpd.dpd_backward(pa, st, 0, P(self.u), P(self.gy), P(self.gu), 0, R, N, ld,
+                              P(self.ws), self.ws_bytes)
+            _dpd.dpd_backward(iq, st, 0, P(self.z), P(self.gu), P(self.gz), 0, R, N, ld,
+                              P(self.ws), self.ws_bytes)
         _dpd.dpd_backward(self.plan.handle, st, P(self.coeffs), P(self.x), P(self.gz), 0, P(self.gc),
                           R, N, ld, P(self.ws), self.ws_bytes)
         self.t += 1
