@@ -21,20 +21,38 @@ namespace dpd {
 
 constexpr int kLossBlocks = 1024;
 
+// Chunks of 2 kBlock samples: block b takes chunks b, b + grid, ... (the
+// blocks running together sweep memory in order), two samples per lane with
+// 16-byte accesses when every buffer is 16-byte aligned.  Fixed assignment and
+// order: deterministic.
 __global__ void __launch_bounds__(kBlock) loss_kernel(const float2 *__restrict__ y, const float2 *__restrict__ x,
                                                       int64_t n, float s, float gscale, float2 *__restrict__ gy,
-                                                      float *__restrict__ partials)
+                                                      float *__restrict__ partials, int vec)
 {
     __shared__ float red[kBlock];
-    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)blockIdx.x * per;
-    const int64_t hi = lo + per < n ? lo + per : n;
+    constexpr int64_t CH = 2 * kBlock;
     float acc = 0.f;
-    for (int64_t t = lo + threadIdx.x; t < hi; t += kBlock) {
-        const float2 a = y[t], b = x[t];
+    const auto one = [&](float2 a, float2 b) {
         const float rr = __builtin_fmaf(s, a.x, -b.x), ri = __builtin_fmaf(s, a.y, -b.y);
         acc = __builtin_fmaf(rr, rr, __builtin_fmaf(ri, ri, acc));
-        if (gy != nullptr) gy[t] = make_float2(gscale * rr, gscale * ri);
+        return make_float2(gscale * rr, gscale * ri);
+    };
+    for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < n; c0 += (int64_t)gridDim.x * CH) {
+        const int64_t t = c0 + 2 * (int64_t)threadIdx.x;
+        if (vec && t + 1 < n) {
+            const float4 a = *reinterpret_cast<const float4 *>(y + t);
+            const float4 b = *reinterpret_cast<const float4 *>(x + t);
+            const float2 g0 = one(make_float2(a.x, a.y), make_float2(b.x, b.y));
+            const float2 g1 = one(make_float2(a.z, a.w), make_float2(b.z, b.w));
+            if (gy != nullptr) *reinterpret_cast<float4 *>(gy + t) = make_float4(g0.x, g0.y, g1.x, g1.y);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                if (t + i < n) {
+                    const float2 g0 = one(y[t + i], x[t + i]);
+                    if (gy != nullptr) gy[t + i] = g0;
+                }
+        }
     }
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -516,8 +534,9 @@ DPD_EXPORT dpd_status dpd_loss_grad(void *stream, const void *y, const void *x, 
     if (n > 0) {
         nblk = (int)std::min<int64_t>(kLossBlocks, (n + kBlock - 1) / kBlock);
         const float gscale = (float)(2.0 * scale / (double)n);
+        const int vec = ((uintptr_t)y % 16 == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)grad_y % 16 == 0) ? 1 : 0;
         hipLaunchKernelGGL(loss_kernel, dim3(nblk), dim3(kBlock), 0, st, (const float2 *)y, (const float2 *)x, n,
-                           scale, gscale, (float2 *)grad_y, (float *)ws);
+                           scale, gscale, (float2 *)grad_y, (float *)ws, vec);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e);
     }

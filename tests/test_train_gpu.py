@@ -81,3 +81,27 @@ def test_config5_training_and_resume(torch):
     for _ in range(100):
         c.step()
     assert torch.equal(c.coeffs, a.coeffs)
+
+
+@pytest.mark.parametrize("n,off", [(100003, 0), (100003, 1), (1, 0), (2049, 1)])
+def test_loss_grad_against_fp64(torch, n, off):
+    """dpd_loss_grad on 16-byte aligned buffers (two samples per access) and on
+    8-byte aligned ones (one per access), odd lengths included."""
+    from paper_1612_09001_amd import dpd
+
+    y = signals.ofdm_16qam(n + off, config_id=77)
+    x = signals.ofdm_16qam(n + off, config_id=78)
+    yd = torch.from_numpy(y).cuda()[off:]
+    xd = torch.from_numpy(x).cuda()[off:]
+    gy = torch.empty(n + off, dtype=torch.complex64, device="cuda")[off:]
+    loss = torch.zeros(1, device="cuda")
+    wsb = dpd.dpd_loss_ws_size(n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    dpd.dpd_loss_grad(dpd.current_stream(), yd.data_ptr(), xd.data_ptr(), n, 0.1, loss.data_ptr(), gy.data_ptr(),
+                      ws.data_ptr(), wsb)
+    r = 0.1 * y[off:].astype(np.complex128) - x[off:].astype(np.complex128)
+    E = float(np.mean(np.abs(r) ** 2))
+    assert abs(float(loss.item()) - E) <= 1e-5 * E
+    g = gy.cpu().numpy()
+    ref = (2 * 0.1 / n) * r
+    assert np.max(np.abs(g - ref)) <= 1e-5 * np.max(np.abs(ref))
