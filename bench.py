@@ -436,16 +436,20 @@ def leg_ls(torch, dpd, signals, reps=5):
         return round(spectral.distortion_regrowth_db(y.cpu().numpy() / est.pa.gain, xh), 2)
 
     out["guard_band_distortion_db_no_dpd"] = regrowth()
+    warm = ila.ILA(x, orders, orders, L)   # first launches of every kernel on the way
+    warm.step()
+    torch.cuda.synchronize()
+    del warm
     e = [est.nmse_db()]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    est.step()
-    torch.cuda.synchronize()
-    out["ila_iteration_ms_2^18"] = round((time.perf_counter() - t0) * 1e3, 3)
-    e.append(est.nmse_db())
-    for _ in range(2):
+    times = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         est.step()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
         e.append(est.nmse_db())
+    out["ila_iteration_ms_2^18"] = round(float(np.median(times)) * 1e3, 3)
     out["ila_nmse_db_iters_0_to_3"] = [round(v, 2) for v in e]
     out["guard_band_distortion_db_after_3_iters"] = regrowth()
     out["ila_solve_info"] = int(est.info.item())

@@ -27,32 +27,58 @@ def identity_coeffs(n_main: int, n_conj: int, L: int) -> np.ndarray:
 class ILA:
     """Iterated least-squares fit of an APH predistorter to the synthetic PA.
 
-    x: complex64 GPU tensor (rows x n or 1-D) of transmit samples.  ridge: the
-    diagonal loading of the normal equations, relative to their mean diagonal.
+    x: contiguous complex64 GPU tensor (rows x n or 1-D) of transmit samples.
+    ridge: the diagonal loading of the normal equations, relative to their mean
+    diagonal.  Every buffer is allocated once here; an iteration is six
+    library calls on the current stream with no host synchronization.
     """
 
     def __init__(self, x, main_orders, conj_orders, L, ridge=1e-9, pa=None):
+        import torch
+
+        if not x.is_contiguous() or x.dim() not in (1, 2):
+            raise ValueError("x must be a contiguous 1-D or rows x n tensor")
         self.x = x
         self.plan = _dpd.Plan(main_orders, conj_orders, L,
                               identity_coeffs(len(main_orders), len(conj_orders), L))
         self.pa = pa if pa is not None else _pa.SyntheticPA()
         self.ridge = float(ridge)
-        self.h = None
-        self.info = None
+        self.rows, self.n = (1, x.numel()) if x.dim() == 1 else tuple(x.shape)
+        dev = x.device
+        K = self.plan.K
+        self.z = torch.empty_like(x)
+        self.u = torch.empty_like(x)
+        self.y = torch.empty_like(x)
+        self.A = torch.empty((K, K), dtype=torch.complex128, device=dev)
+        self.b = torch.empty(K, dtype=torch.complex128, device=dev)
+        self.ws_bytes = _dpd.dpd_ls_ws_size(self.plan.handle, self.rows, self.n)
+        self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=dev)
+        self.sws_bytes = _dpd.dpd_ls_solve_ws_size(K)
+        self.sws = torch.empty(self.sws_bytes, dtype=torch.uint8, device=dev)
+        self.h = torch.zeros(K, dtype=torch.complex64, device=dev)
+        self.info = torch.zeros((), dtype=torch.int32, device=dev)
 
     def transmit(self):
-        """Predistorter then PA: (z, y)."""
-        z = self.plan.apply(self.x)
-        _, y = self.pa.forward(z)
-        return z, y
+        """Predistorter then PA into the resident buffers: (z, y)."""
+        st = _dpd.current_stream()
+        R, N = self.rows, self.n
+        _dpd.dpd_apply_rows(self.plan.handle, st, self.x.data_ptr(), self.z.data_ptr(), R, N, N)
+        _dpd.dpd_apply_rows(self.pa.iq.handle, st, self.z.data_ptr(), self.u.data_ptr(), R, N, N)
+        _dpd.dpd_apply_rows(self.pa.pa.handle, st, self.u.data_ptr(), self.y.data_ptr(), R, N, N)
+        return self.z, self.y
 
     def step(self):
         """One iteration: fit the postdistorter (y / G -> z) and copy it into
         the predistorter.  Returns the device info flag of the solve."""
         z, y = self.transmit()
-        A, b = self.plan.ls_normal(y, z, y_scale=1.0 / self.pa.gain)
-        self.h, self.info = _dpd.ls_solve(A, b, self.ridge)
-        self.plan.set_coeffs(self.h)
+        st = _dpd.current_stream()
+        K = self.plan.K
+        _dpd.dpd_ls_normal(self.plan.handle, st, y.data_ptr(), z.data_ptr(), self.rows, self.n, self.n,
+                           1.0 / self.pa.gain, self.ws.data_ptr(), self.ws_bytes, self.A.data_ptr(),
+                           self.b.data_ptr())
+        _dpd.dpd_ls_solve(st, K, self.A.data_ptr(), self.b.data_ptr(), self.ridge, self.sws.data_ptr(),
+                          self.sws_bytes, self.h.data_ptr(), self.info.data_ptr())
+        _dpd.dpd_set_coeffs_device(self.plan.handle, self.h.data_ptr(), st)
         return self.info
 
     def nmse_db(self) -> float:
