@@ -197,18 +197,28 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
         }
         if (d.n > 0) order.push_back(s);
     }
-    // no stream may write where another reads or writes
-    for (int32_t s = 0; s < n_streams; ++s) {
-        const size_t bs = (size_t)desc[s].n * 8;
-        for (int32_t r = 0; r < n_streams && bs > 0; ++r) {
-            if (r == s || desc[r].n == 0) continue;
-            const size_t br = (size_t)desc[r].n * 8;
-            const uintptr_t o = (uintptr_t)desc[s].out;
-            const uintptr_t i = (uintptr_t)desc[r].in, w = (uintptr_t)desc[r].out;
-            if ((o < i + br && i < o + bs) || (o < w + br && w < o + bs)) {
-                free_batch(b);
-                return DPD_EINVAL;
-            }
+    // No stream may write where any stream reads or another one writes
+    // (inputs may be shared).  Sorted output ranges overlap iff two neighbours
+    // do; each input range is then looked up among them: O(n log n).
+    {
+        std::vector<std::pair<uintptr_t, uintptr_t>> outs;   // [begin, end) of every output
+        for (int32_t s = 0; s < n_streams; ++s)
+            if (desc[s].n > 0)
+                outs.emplace_back((uintptr_t)desc[s].out, (uintptr_t)desc[s].out + (size_t)desc[s].n * 8);
+        std::sort(outs.begin(), outs.end());
+        bool bad = false;
+        for (size_t i = 1; i < outs.size() && !bad; ++i) bad = outs[i].first < outs[i - 1].second;
+        for (int32_t s = 0; s < n_streams && !bad; ++s) {
+            if (desc[s].n == 0) continue;
+            const uintptr_t lo = (uintptr_t)desc[s].in, hi = lo + (size_t)desc[s].n * 8;
+            // the first output ending after lo (ends ascend: the ranges are disjoint and sorted)
+            auto it = std::upper_bound(outs.begin(), outs.end(), lo,
+                                       [](uintptr_t v, const std::pair<uintptr_t, uintptr_t> &o) { return v < o.second; });
+            bad = it != outs.end() && it->first < hi;
+        }
+        if (bad) {
+            free_batch(b);
+            return DPD_EINVAL;
         }
     }
     if (tab_total >= (int64_t)1 << 30) {

@@ -91,3 +91,30 @@ def test_least_squares_argument_checks(lib):
                             fake) == dpd.DPD_EINVAL  # workspace too small
     assert lib.dpd_ls_solve(None, 1025, fake, fake, ctypes.c_double(0.0), fake, 1 << 30, fake,
                             fake) == dpd.DPD_EUNSUPPORTED  # more rows than one wave holds
+
+
+def test_batch_rejects_overlapping_streams(lib):
+    """Outputs may not overlap each other or any input; inputs may be shared.
+    Checked on the host before any device call (fake, never dereferenced,
+    16-byte aligned addresses)."""
+    base = 1 << 24
+
+    def desc(i, o, n):
+        return dpd.dpd_stream_desc(base + i, base + o, n, 1, 0, 2, 0, base)
+
+    def create(ds):
+        arr = (dpd.dpd_stream_desc * len(ds))(*ds)
+        h = ctypes.c_void_p()
+        st = lib.dpd_batch_create(arr, len(ds), None, ctypes.byref(h))
+        if st == dpd.DPD_OK:
+            lib.dpd_batch_destroy(h)
+        return st
+
+    many = [desc(0x100000 + 0x1000 * s, 0x800000 + 0x1000 * s, 512) for s in range(1000)]
+    assert create([desc(0x10000, 0x20000, 100), desc(0x30000, 0x20000 + 8 * 48, 100)]) == dpd.DPD_EINVAL
+    assert create([desc(0x10000, 0x20000, 100), desc(0x20000 + 8 * 99, 0x40000, 100)]) == dpd.DPD_EINVAL
+    assert create(many + [desc(0x50000, 0x800000 + 0x1000 * 999 + 8 * 511, 4)]) == dpd.DPD_EINVAL
+    # shared inputs and touching (not overlapping) ranges pass the check (then
+    # need a device: DPD_OK on a GPU, DPD_EHIP without one)
+    assert create([desc(0x10000, 0x20000, 100), desc(0x10000, 0x20000 + 8 * 100, 100)]) != dpd.DPD_EINVAL
+    assert create(many) != dpd.DPD_EINVAL
