@@ -13,11 +13,14 @@
 //     Re A = R_rr + R_ii,      Im A = R_ri - R_ri^T,
 //     Re b = R_r,t_r + R_i,t_i,  Im b = R_r,t_i - R_i,t_r.
 // R is a dense contraction over samples, so it runs on the matrix cores:
-// v_mfma_f32_16x16x4f32 over 16x16 tiles of the upper triangle of R, the
-// features of 64 samples at a time staged in LDS.  Each block covers one slab
+// v_mfma_f32_16x16x32_bf16 over 16x16 tiles of the upper triangle of R, the
+// features of 64 samples at a time staged in LDS, each FP32 feature as a bf16
+// high part and the bf16 rounding of its remainder; the four cross products of
+// every pair of features are summed in FP32 (the dropped terms are ~2^-17 of
+// each product, below FP32 accumulation error).  Each block covers one slab
 // of 1024..4096 samples (the size depends only on the input shape and the
 // number of CUs) and writes its FP32 tiles (each of the four waves adds at
-// most 256 four-product steps per accumulator; the four partial tiles are
+// most 128 eight-sample steps per accumulator; the four partial tiles are
 // summed in FP32); the slabs are summed in FP64 in a fixed order (two
 // levels), so the result is deterministic.
 #include <hip/hip_runtime.h>
@@ -35,6 +38,8 @@
 namespace dpd {
 
 typedef float v4f_ls __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_ls __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4_ls __attribute__((ext_vector_type(4)));
 
 constexpr int kLsTile = 64;         // samples staged per step
 constexpr int kLsSolveMaxK = 1024;  // one wave, at most 16 rows per lane
@@ -96,15 +101,40 @@ constexpr int ls_pair_j(int q, int nt)
 // 1.21 ms, +4 1.30 ms, +8 1.48 ms per 2^24 samples.
 constexpr int ls_stride(int nt) { return 16 * nt + 1; }
 
-// One 4-sample step of the pairs Q0, Q0 + 1, ...: the operand blocks of each
-// pair are compile-time constants (forced), so the operands stay in fixed
-// registers.
-template <int NT, int Q0, int... U>
-__device__ __forceinline__ void ls_gram_step(v4f_ls *acc, const float *op, std::integer_sequence<int, U...>)
+// A feature as its bf16 high part (low half) and the bf16 rounding of the
+// remainder (high half): f = hi + lo to about 2^-16 relative, so the four
+// cross products of two features carry FP32-level accuracy.
+__device__ __forceinline__ uint32_t ls_pack(float f)
 {
-    ((acc[U] = __builtin_amdgcn_mfma_f32_16x16x4f32(op[std::integral_constant<int, ls_pair_i(Q0 + U, NT)>::value],
-                                                    op[std::integral_constant<int, ls_pair_j(Q0 + U, NT)>::value],
-                                                    acc[U], 0, 0, 0)),
+    const __bf16 h = (__bf16)f;
+    const __bf16 l = (__bf16)(f - (float)h);
+    return (uint32_t)__builtin_bit_cast(unsigned short, h) | ((uint32_t)__builtin_bit_cast(unsigned short, l) << 16);
+}
+
+typedef float f32x2_ls __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_ls __attribute__((ext_vector_type(2)));
+
+// ls_pack of two values with two packed conversions (round to nearest even).
+__device__ __forceinline__ void ls_pack2(float a, float b, uint32_t &wa, uint32_t &wb)
+{
+    const uint32_t hw = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_ls{a, b}, bf16x2_ls));
+    const float ha = __uint_as_float(hw << 16), hb = __uint_as_float(hw & 0xffff0000u);
+    const uint32_t lw = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_ls{a - ha, b - hb}, bf16x2_ls));
+    wa = (hw & 0xffffu) | (lw << 16);
+    wb = (hw >> 16) | (lw & 0xffff0000u);
+}
+
+// One 8-sample step of the pairs Q0, Q0 + 1, ...: a[b] / c[b] are operand
+// block b as (hi, lo, hi, lo) per sample and as (hi, lo, lo, hi), so every
+// sample contributes hi hi' + lo lo' + hi lo' + lo hi'.  The blocks of each
+// pair are compile-time constants (forced).
+template <int NT, int Q0, int... U>
+__device__ __forceinline__ void ls_gram_step(v4f_ls *acc, const bf16x8_ls *a, const bf16x8_ls *c,
+                                             std::integer_sequence<int, U...>)
+{
+    ((acc[U] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[std::integral_constant<int, ls_pair_i(Q0 + U, NT)>::value],
+                                                       c[std::integral_constant<int, ls_pair_j(Q0 + U, NT)>::value],
+                                                       acc[U], 0, 0, 0)),
      ...);
 }
 
@@ -123,7 +153,7 @@ constexpr int ls_pair_groups(int nt) { return nt * (nt + 1) / 2 * 4 <= 128 ? 1 :
 // has no conditionals (a guarded accumulation becomes a branch whose merge
 // copies every accumulator) and every wave runs the same code.
 template <int NT, int G>
-__device__ __forceinline__ void ls_gram_wave(const LsParams &p, float (*X)[ls_stride(NT)], int64_t slab, int64_t s0,
+__device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[ls_stride(NT)], int64_t slab, int64_t s0,
                                              int64_t send, const float2 *yr, const float2 *tr)
 {
     constexpr int NP = NT * (NT + 1) / 2;
@@ -163,7 +193,7 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, float (*X)[ls_st
         // x 4 columns, all loop-invariant) from being hoisted into registers
         int z = 0;
         asm volatile("" : "+v"(z));
-        float *xs = X[s] + z;
+        uint32_t *xs = X[s] + z;
         if (m < p.n) {
 #pragma unroll
             for (int i = 0; i < KT; ++i) {
@@ -174,42 +204,54 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, float (*X)[ls_st
                     float pw = 1.f;
 #pragma unroll
                     for (int j = 0; j < kMaxNI; ++j) {
-                        const float a = pw * v.x, b = pw * v.y;
+                        uint32_t wa, wb;
+                        ls_pack2(pw * v.x, pw * v.y, wa, wb);
                         if (j < p.NI && p.cm[j] >= 0) {
-                            xs[p.cm[j] + k] = a;
-                            xs[p.K + p.cm[j] + k] = b;
+                            xs[p.cm[j] + k] = wa;
+                            xs[p.K + p.cm[j] + k] = wb;
                         }
                         if (j < p.NI && p.cc[j] >= 0) {
-                            xs[p.cc[j] + k] = a;
-                            xs[p.K + p.cc[j] + k] = -b;
+                            xs[p.cc[j] + k] = wa;
+                            xs[p.K + p.cc[j] + k] = wb ^ 0x80008000u;   // -b: both parts negated exactly
                         }
                         pw *= s2;
                     }
                 }
             }
             if (part == 0) {
-                xs[p.K - 1] = 1.f;
-                xs[2 * p.K - 1] = 0.f;
-                xs[2 * p.K] = tv.x;
-                xs[2 * p.K + 1] = tv.y;
+                xs[p.K - 1] = ls_pack(1.f);
+                xs[2 * p.K - 1] = 0u;
+                uint32_t ta, tb;
+                ls_pack2(tv.x, tv.y, ta, tb);
+                xs[2 * p.K] = ta;
+                xs[2 * p.K + 1] = tb;
             }
         } else {
-            for (int f = part; f < p.D; f += kLsWaves) xs[f] = 0.f;
+            for (int f = part; f < p.D; f += kLsWaves) xs[f] = 0u;
         }
         __syncthreads();
         if (m0 + kLsTile < send) fetch(m0 + kLsTile);
-        // tile (I, J) += X[:, 16I..16I+15]^T X[:, 16J..16J+15], 4 samples per step:
-        // lane l feeds row / column l % 16 of sample l / 16 of the step.  A
-        // step's operand blocks are loaded once and feed every pair; a
-        // scheduling barrier per step keeps one step's operands in registers.
-        const int r = lane >> 4, c = lane & 15;
+        // tile (I, J) += X[:, 16I..16I+15]^T X[:, 16J..16J+15], 8 samples per step:
+        // lane l feeds row / column l % 16 and samples 2 (l / 16), 2 (l / 16) + 1
+        // of the step (four slots each).  A step's operand blocks are read once
+        // (one ds_read2 per block) and feed every pair; a scheduling barrier per
+        // step keeps one step's operands in registers.
+        const int g2 = 2 * (lane >> 4), c = lane & 15;
 #pragma unroll
-        for (int i = 0; i < kLsTile / 4 / GK; ++i) {
-            const float *xr = X[4 * (kw + GK * i) + r];
-            float op[NT];   // blocks no pair of the group uses are never loaded
+        for (int i = 0; i < kLsTile / 8 / GK; ++i) {
+            const uint32_t *x0 = X[8 * (kw + GK * i) + g2] + c;
+            bf16x8_ls a[NT], cb[NT];   // blocks no pair of the group uses are never loaded
 #pragma unroll
-            for (int b = 0; b < NT; ++b) op[b] = xr[16 * b + c];
-            ls_gram_step<NT, Q0>(acc, op, std::make_integer_sequence<int, PW>{});
+            for (int b = 0; b < NT; ++b) {
+                const uint32_t w0 = x0[16 * b], w1 = x0[ls_stride(NT) + 16 * b];
+                // (hi, lo) twice against (hi', lo') then (lo', hi'): the two
+                // slot pairs of a sample give hi hi' + lo lo' and hi lo' + lo hi'
+                const u32x4_ls av = {w0, w0, w1, w1};
+                const u32x4_ls bv = {w0, __builtin_amdgcn_alignbit(w0, w0, 16), w1, __builtin_amdgcn_alignbit(w1, w1, 16)};
+                a[b] = __builtin_bit_cast(bf16x8_ls, av);
+                cb[b] = __builtin_bit_cast(bf16x8_ls, bv);
+            }
+            ls_gram_step<NT, Q0>(acc, a, cb, std::make_integer_sequence<int, PW>{});
             __builtin_amdgcn_sched_barrier(0);
         }
     }
@@ -217,7 +259,7 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, float (*X)[ls_st
     // accumulators (pair u of their group) in LDS, then the waves of a group
     // each add up 4 / GK of the register slots, in wave order.  Tile element
     // (4 (l / 16) + v, l % 16) is register v of lane l.
-    float *buf = &X[0][0];   // 4 x 256 floats (the tile of 64 x ls_stride(NT) >= 1088 floats)
+    float *buf = reinterpret_cast<float *>(&X[0][0]);   // 4 x 256 floats (the tile: 64 x ls_stride(NT) >= 1088 words)
     float *out = p.partials + (slab * NP + Q0) * 256;
     const int wv = tid >> 6;
     for (int u = 0; u < PP; ++u) {
@@ -249,7 +291,7 @@ template <int NT>
 __global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
 {
     static_assert(kLsTile * ls_stride(NT) >= kLsWaves * 256, "LDS tile too small for the final sums");
-    __shared__ float X[kLsTile][ls_stride(NT)];
+    __shared__ uint32_t X[kLsTile][ls_stride(NT)];
     const int tid = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t slab = blockIdx.x;
@@ -259,7 +301,7 @@ __global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
     const float2 *tr = p.t + row * p.ld;
     const int pad = p.Dp - p.D;
     if (pad > 0)
-        for (int e = tid; e < kLsTile * pad; e += kBlock) X[e / pad][p.D + e % pad] = 0.f;
+        for (int e = tid; e < kLsTile * pad; e += kBlock) X[e / pad][p.D + e % pad] = 0u;
     const int64_t send = std::min<int64_t>(s0 + p.slab, p.n);
     if constexpr (ls_pair_groups(NT) == 1) {
         ls_gram_wave<NT, 0>(p, X, slab, s0, send, yr, tr);

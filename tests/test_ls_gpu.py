@@ -11,10 +11,12 @@ pytestmark = pytest.mark.gpu
 
 # Scaled-Frobenius tolerance of the normal equations.  Features are FP32
 # (order 2j+1 by j repeated multiplications: relative error <= ~(2j+2) 2^-24
-# <= 1.2e-6 for order 9); each FP32 accumulator adds at most 256 four-product
-# steps and the four wave partials of a slab are added in FP32 before the FP64
-# slab sum (relative error ~ sqrt(260) 2^-24 = 1e-6 for random rounding,
-# 1.6e-5 worst case).  2e-5 sits above the worst case.
+# <= 1.2e-6 for order 9); on the matrix cores each is a bf16 high part plus the
+# bf16 rounding of the remainder, whose four cross products leave ~2^-17 of
+# each product, random in sign; each FP32 accumulator adds at most 128
+# eight-sample steps and the four wave partials of a slab are added in FP32
+# before the FP64 slab sum (relative error ~1e-6 for random rounding; measured
+# 2e-7..9e-7 on A and ~3e-6 on b).  2e-5 leaves a margin of 6 or more.
 LS_REL_MAX = 2e-5
 
 
