@@ -175,26 +175,31 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[ls
     constexpr int KT = kMaxL / kLsWaves;
     float2 yv[KT];
     float2 tv = make_float2(0.f, 0.f);
-    auto fetch = [&](int64_t m0) {
-        const int64_t m = m0 + s;
+    // 32-bit sample indices relative to the slab start: nl samples in the
+    // slab, inputs valid from index lo on (the row start, or L taps back)
+    const float2 *ys = yr + s0, *ts = tr + s0;
+    const int nl = (int)(send - s0);
+    const int lo = s0 >= kMaxL ? -kMaxL : (int)-s0;
+    auto fetch = [&](int m0) {
+        const int m = m0 + s;
 #pragma unroll
         for (int i = 0; i < KT; ++i) {
             const int k = part + kLsWaves * i;
-            const int64_t mk = m - k;
-            yv[i] = (k < p.L && m < p.n && mk >= 0) ? yr[mk] : make_float2(0.f, 0.f);
+            const int mk = m - k;
+            yv[i] = (k < p.L && m < nl && mk >= lo) ? ys[mk] : make_float2(0.f, 0.f);
         }
-        tv = (part == 0 && m < p.n) ? tr[m] : make_float2(0.f, 0.f);
+        tv = (part == 0 && m < nl) ? ts[m] : make_float2(0.f, 0.f);
     };
-    fetch(s0);
-    for (int64_t m0 = s0; m0 < send; m0 += kLsTile) {
+    fetch(0);
+    for (int m0 = 0; m0 < nl; m0 += kLsTile) {
         __syncthreads();   // the previous tile's matrix-core reads are done
-        const int64_t m = m0 + s;
+        const int m = m0 + s;
         // an opaque zero keeps the feature addresses (up to 4 taps x 8 levels
         // x 4 columns, all loop-invariant) from being hoisted into registers
         int z = 0;
         asm volatile("" : "+v"(z));
         uint32_t *xs = X[s] + z;
-        if (m < p.n) {
+        if (m < nl) {
 #pragma unroll
             for (int i = 0; i < KT; ++i) {
                 const int k = part + kLsWaves * i;
@@ -230,7 +235,7 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[ls
             for (int f = part; f < p.D; f += kLsWaves) xs[f] = 0u;
         }
         __syncthreads();
-        if (m0 + kLsTile < send) fetch(m0 + kLsTile);
+        if (m0 + kLsTile < nl) fetch(m0 + kLsTile);
         // tile (I, J) += X[:, 16I..16I+15]^T X[:, 16J..16J+15], 8 samples per step:
         // lane l feeds row / column l % 16 and samples 2 (l / 16), 2 (l / 16) + 1
         // of the step (four slots each).  A step's operand blocks are read once
