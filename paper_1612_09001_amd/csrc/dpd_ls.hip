@@ -13,9 +13,10 @@
 //     Re A = R_rr + R_ii,      Im A = R_ri - R_ri^T,
 //     Re b = R_r,t_r + R_i,t_i,  Im b = R_r,t_i - R_i,t_r.
 // R is a dense contraction over samples, so it runs on the matrix cores:
-// v_mfma_f32_16x16x32_bf16 over 16x16 tiles of the upper triangle of R, the
-// features of 64 samples at a time staged in LDS, each FP32 feature as a bf16
-// high part and the bf16 rounding of its remainder; the four cross products of
+// v_mfma_f32_16x16x32_bf16 over 16x16 tiles of the upper triangle of R.  The
+// basis psi_j of 64 samples at a time (and of the L - 1 before them) is staged
+// in LDS once per input sample, each FP32 value as a bf16 high part and the
+// bf16 rounding of its remainder, and the tap columns read it shifted; the four cross products of
 // every pair of features are summed in FP32 (the dropped terms are ~2^-17 of
 // each product, below FP32 accumulation error).  Each block covers one slab
 // of 1024..4096 samples (the size depends only on the input shape and the
@@ -60,8 +61,7 @@ struct LsParams {
     float *partials;        // [slab][pair][256]
     int K, D, Dp, nt, npairs;
     int L, NI;
-    int16_t cm[kMaxNI];     // first column of the main-branch taps of level j, or -1
-    int16_t cc[kMaxNI];     // the same for the conjugate branch
+    int16_t off[kLsMaxDp];  // LDS word of feature f relative to the basis row of the sample
 };
 
 // Tile pair q of the upper triangle, row-major over (I <= J).
@@ -94,12 +94,6 @@ constexpr int ls_pair_j(int q, int nt)
     }
     return I + q;
 }
-
-// LDS row stride (floats) for NT column tiles: 16 NT + 1.  Small, so that
-// more blocks share a CU; odd, so that the feature stores (one sample per
-// lane) hit distinct banks.  Measured on K = 33 (16 NT = 80): +0 1.75 ms, +1
-// 1.21 ms, +4 1.30 ms, +8 1.48 ms per 2^24 samples.
-constexpr int ls_stride(int nt) { return 16 * nt + 1; }
 
 // A feature as its bf16 high part (low half) and the bf16 rounding of the
 // remainder (high half): f = hi + lo to about 2^-16 relative, so the four
@@ -143,17 +137,71 @@ __device__ __forceinline__ void ls_gram_step(v4f_ls *acc, const bf16x8_ls *a, co
 // else two (two waves per group).
 constexpr int ls_pair_groups(int nt) { return nt * (nt + 1) / 2 * 4 <= 128 ? 1 : 2; }
 
+// The basis of a tile in LDS: one row per input sample (the tile's 64 samples
+// and the L - 1 before them), holding psi_j of that sample as packed words
+// (Re, Im and -Im of every power level), the constant 1 (0 outside the slab),
+// a zero word and the target t, each entry twice (two equal words, so that
+// one 64-bit read per sample gives the row-side operand).  Row m of Psi
+// repeats the rows of samples m, m-1, ..., m-L+1 (Eq. 2 is Toeplitz in the
+// taps), so each Gram column f reads the word off[f] = (L - 1 - k) stride +
+// 2 entry(f) relative to row m.
+constexpr int kLsBEntries = 3 * kMaxNI + 5;        // 3 NI + 4 entries per row, odd
+constexpr int kLsBStride = 2 * kLsBEntries;        // words per row
+constexpr int kLsWIm = kMaxNI, kLsWNegIm = 2 * kMaxNI;
+constexpr int kLsWOne = 3 * kMaxNI, kLsWZero = kLsWOne + 1, kLsWT = kLsWOne + 2;
+constexpr int kLsRows = kLsTile + kMaxL - 1;
+
+// One 64-sample tile of the matrix phase.  Lane l feeds row / column l % 16
+// and samples 2 (l / 16), 2 (l / 16) + 1 of each 8-sample step (four slots
+// each); a step's operand blocks are read once and feed every pair; a
+// scheduling barrier per step keeps one step's operands in registers.  With
+// MASK the samples at or past vt (the end of the slab) contribute nothing:
+// their row-side operands are zeroed.
+template <int NT, int Q0, int PW, int GK, bool MASK>
+__device__ __forceinline__ void ls_gram_tile(v4f_ls *acc, const uint32_t *Xf, const int *addr, int kw, int g2,
+                                             int vt)
+{
+#pragma unroll
+    for (int i = 0; i < kLsTile / 8 / GK; ++i) {
+        const int row = 8 * GK * i;   // step kw + GK i, relative to the wave's first step
+        bf16x8_ls a[NT], cb[NT];      // blocks no pair of the group uses are never loaded
+        bool ok0 = true, ok1 = true;
+        if constexpr (MASK) {
+            const int m = 8 * (kw + GK * i) + g2;
+            ok0 = m < vt;
+            ok1 = m + 1 < vt;
+        }
+#pragma unroll
+        for (int b = 0; b < NT; ++b) {
+            const uint2 p0 = *reinterpret_cast<const uint2 *>(Xf + addr[b] + row * kLsBStride);
+            const uint2 p1 = *reinterpret_cast<const uint2 *>(Xf + addr[b] + (row + 1) * kLsBStride);
+            // (hi, lo) twice against (hi', lo') then (lo', hi'): the two slot
+            // pairs of a sample give hi hi' + lo lo' and hi lo' + lo hi'
+            const u32x4_ls av = MASK ? u32x4_ls{ok0 ? p0.x : 0u, ok0 ? p0.y : 0u, ok1 ? p1.x : 0u, ok1 ? p1.y : 0u}
+                                     : u32x4_ls{p0.x, p0.y, p1.x, p1.y};
+            const u32x4_ls bv = {p0.x, __builtin_amdgcn_alignbit(p0.y, p0.y, 16), p1.x,
+                                 __builtin_amdgcn_alignbit(p1.y, p1.y, 16)};
+            a[b] = __builtin_bit_cast(bf16x8_ls, av);
+            cb[b] = __builtin_bit_cast(bf16x8_ls, bv);
+        }
+        ls_gram_step<NT, Q0>(acc, a, cb, std::make_integer_sequence<int, PW>{});
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // One wave's part of a slab.  The waves of pair group G (GK = 4 / GP of
 // them) accumulate the tile pairs [G PP, (G + 1) PP) of the row-major upper
-// triangle, each over every GK-th 4-sample step of each 64-sample tile, so
+// triangle, each over every GK-th 8-sample step of each 64-sample tile, so
 // a step loads each 16-column operand block once for all of its pairs.  All
-// four waves build the features of each tile together (barriers).  At the
-// end the GK partial tiles of each pair are summed through LDS (fixed order)
-// and written out.  The pair list is a compile-time constant: the matrix loop
-// has no conditionals (a guarded accumulation becomes a branch whose merge
-// copies every accumulator) and every wave runs the same code.
+// four waves build the basis rows of each tile together (barriers): wave w
+// the power levels [w lpw, (w + 1) lpw), the last wave also the constant and
+// target words.  At the end the GK partial tiles of each pair are summed
+// through LDS (fixed order) and written out.  The pair list is a compile-time
+// constant: the matrix loop has no conditionals (a guarded accumulation
+// becomes a branch whose merge copies every accumulator) and every wave runs
+// the same code.
 template <int NT, int G>
-__device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[ls_stride(NT)], int64_t slab, int64_t s0,
+__device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kLsBStride], int64_t slab, int64_t s0,
                                              int64_t send, const float2 *yr, const float2 *tr)
 {
     constexpr int NP = NT * (NT + 1) / 2;
@@ -163,110 +211,105 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[ls
     constexpr int Q0 = G * PP;
     constexpr int PW = NP - Q0 < PP ? NP - Q0 : PP;   // pairs of this group
     const int tid = threadIdx.x, lane = tid & 63;
-    const int kw = (tid >> 6) % GK;                   // this wave's steps: kw, kw + GK, ...
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int kw = wv % GK;                           // this wave's steps: kw, kw + GK, ...
     v4f_ls acc[PW];
 #pragma unroll
     for (int u = 0; u < PW; ++u) acc[u] = v4f_ls{0.f, 0.f, 0.f, 0.f};
 
-    const int s = tid & (kLsTile - 1);   // sample of the tile this thread builds
-    const int part = tid / kLsTile;      // taps part, part + 4, ...
-    // The samples a thread needs for a tile (y_{m-k} for its taps, t_m) are
-    // loaded one tile ahead, during the previous tile's matrix-core phase.
-    constexpr int KT = kMaxL / kLsWaves;
-    float2 yv[KT];
-    float2 tv = make_float2(0.f, 0.f);
-    // 32-bit sample indices relative to the slab start: nl samples in the
-    // slab, inputs valid from index lo on (the row start, or L taps back)
+    // operand addresses (words) of the lane's column in each block, at the
+    // wave's first step
+    const int g2 = 2 * (lane >> 4), c = lane & 15;
+    int addr[NT];
+#pragma unroll
+    for (int b = 0; b < NT; ++b) addr[b] = (8 * kw + g2) * kLsBStride + p.off[16 * b + c];
+
+    // Basis rows r = lane and r = lane + 64 (when below R) of each tile: the
+    // samples (and targets) are loaded one tile ahead, during the previous
+    // tile's matrix phase.  32-bit sample indices relative to the slab start:
+    // nl samples in the slab, inputs valid from index lo on (the row start, or
+    // kMaxL samples back).
+    const int H = p.L - 1;
+    const bool two = lane < H;
+    const bool last = wv == kLsWaves - 1;
+    const int lpw = (p.NI + kLsWaves - 1) / kLsWaves;
+    const int j0 = wv * lpw, nj = std::min(p.NI - j0, lpw);
     const float2 *ys = yr + s0, *ts = tr + s0;
     const int nl = (int)(send - s0);
     const int lo = s0 >= kMaxL ? -kMaxL : (int)-s0;
+    // (zeros as literals: a named zero turns the guarded loads into flat
+    // loads through a pointer select, with the zero in scratch memory)
+    float2 y0 = make_float2(0.f, 0.f), y1 = y0, t0 = y0, t1 = y0;
     auto fetch = [&](int m0) {
-        const int m = m0 + s;
-#pragma unroll
-        for (int i = 0; i < KT; ++i) {
-            const int k = part + kLsWaves * i;
-            const int mk = m - k;
-            yv[i] = (k < p.L && m < nl && mk >= lo) ? ys[mk] : make_float2(0.f, 0.f);
+        const int q0 = m0 - H + lane, q1 = q0 + 64;
+        y0 = (q0 < nl && q0 >= lo) ? ys[q0] : make_float2(0.f, 0.f);
+        y1 = (two && q1 < nl) ? ys[q1] : make_float2(0.f, 0.f);
+        if (last) {
+            t0 = (lane >= H && q0 < nl) ? ts[q0] : make_float2(0.f, 0.f);
+            t1 = (two && q1 < nl) ? ts[q1] : make_float2(0.f, 0.f);
         }
-        tv = (part == 0 && m < nl) ? ts[m] : make_float2(0.f, 0.f);
     };
-    fetch(0);
-    for (int m0 = 0; m0 < nl; m0 += kLsTile) {
+    // psi_j for j in [j0, j0 + nj) of sample y into row x (nj <= 2 uniform)
+    auto put = [](uint32_t *x, int e, uint32_t w) {
+        x[2 * e] = w;
+        x[2 * e + 1] = w;
+    };
+    auto levels = [&](uint32_t *x, float2 y) {
+        const float vx = p.y_scale * y.x, vy = p.y_scale * y.y;
+        const float s2 = __builtin_fmaf(vx, vx, vy * vy);
+        float pw = 1.f;
+        for (int e = 0; e < j0; ++e) pw *= s2;
+#pragma unroll
+        for (int u = 0; u < (kMaxNI + kLsWaves - 1) / kLsWaves; ++u) {
+            if (u < nj) {
+                uint32_t wa, wb;
+                ls_pack2(pw * vx, pw * vy, wa, wb);
+                put(x, j0 + u, wa);
+                put(x, kLsWIm + j0 + u, wb);
+                put(x, kLsWNegIm + j0 + u, wb ^ 0x80008000u);   // -b: both parts negated exactly
+                pw *= s2;
+            }
+        }
+    };
+    auto target = [&](uint32_t *x, float2 t, bool in) {
+        uint32_t ta, tb;
+        ls_pack2(t.x, t.y, ta, tb);
+        put(x, kLsWOne, in ? ls_pack(1.f) : 0u);
+        put(x, kLsWZero, 0u);
+        put(x, kLsWT, ta);
+        put(x, kLsWT + 1, tb);
+    };
+    auto build = [&](int m0) {
         __syncthreads();   // the previous tile's matrix-core reads are done
-        const int m = m0 + s;
-        // an opaque zero keeps the feature addresses (up to 4 taps x 8 levels
-        // x 4 columns, all loop-invariant) from being hoisted into registers
-        int z = 0;
-        asm volatile("" : "+v"(z));
-        uint32_t *xs = X[s] + z;
-        if (m < nl) {
-#pragma unroll
-            for (int i = 0; i < KT; ++i) {
-                const int k = part + kLsWaves * i;
-                if (k < p.L) {
-                    const float2 v = make_float2(p.y_scale * yv[i].x, p.y_scale * yv[i].y);
-                    const float s2 = __builtin_fmaf(v.x, v.x, v.y * v.y);
-                    float pw = 1.f;
-#pragma unroll
-                    for (int j = 0; j < kMaxNI; ++j) {
-                        uint32_t wa, wb;
-                        ls_pack2(pw * v.x, pw * v.y, wa, wb);
-                        if (j < p.NI && p.cm[j] >= 0) {
-                            xs[p.cm[j] + k] = wa;
-                            xs[p.K + p.cm[j] + k] = wb;
-                        }
-                        if (j < p.NI && p.cc[j] >= 0) {
-                            xs[p.cc[j] + k] = wa;
-                            xs[p.K + p.cc[j] + k] = wb ^ 0x80008000u;   // -b: both parts negated exactly
-                        }
-                        pw *= s2;
-                    }
-                }
-            }
-            if (part == 0) {
-                xs[p.K - 1] = ls_pack(1.f);
-                xs[2 * p.K - 1] = 0u;
-                uint32_t ta, tb;
-                ls_pack2(tv.x, tv.y, ta, tb);
-                xs[2 * p.K] = ta;
-                xs[2 * p.K + 1] = tb;
-            }
-        } else {
-            for (int f = part; f < p.D; f += kLsWaves) xs[f] = 0u;
+        levels(X[lane], y0);
+        if (two) levels(X[lane + 64], y1);
+        if (last) {
+            // row r holds sample m0 - H + r; tile samples are rows H..H+63
+            target(X[lane], t0, lane >= H && m0 - H + lane < nl);
+            if (two) target(X[lane + 64], t1, m0 + 64 - H + lane < nl);
         }
         __syncthreads();
         if (m0 + kLsTile < nl) fetch(m0 + kLsTile);
-        // tile (I, J) += X[:, 16I..16I+15]^T X[:, 16J..16J+15], 8 samples per step:
-        // lane l feeds row / column l % 16 and samples 2 (l / 16), 2 (l / 16) + 1
-        // of the step (four slots each).  A step's operand blocks are read once
-        // (one ds_read2 per block) and feed every pair; a scheduling barrier per
-        // step keeps one step's operands in registers.
-        const int g2 = 2 * (lane >> 4), c = lane & 15;
-#pragma unroll
-        for (int i = 0; i < kLsTile / 8 / GK; ++i) {
-            const uint32_t *x0 = X[8 * (kw + GK * i) + g2] + c;
-            bf16x8_ls a[NT], cb[NT];   // blocks no pair of the group uses are never loaded
-#pragma unroll
-            for (int b = 0; b < NT; ++b) {
-                const uint32_t w0 = x0[16 * b], w1 = x0[ls_stride(NT) + 16 * b];
-                // (hi, lo) twice against (hi', lo') then (lo', hi'): the two
-                // slot pairs of a sample give hi hi' + lo lo' and hi lo' + lo hi'
-                const u32x4_ls av = {w0, w0, w1, w1};
-                const u32x4_ls bv = {w0, __builtin_amdgcn_alignbit(w0, w0, 16), w1, __builtin_amdgcn_alignbit(w1, w1, 16)};
-                a[b] = __builtin_bit_cast(bf16x8_ls, av);
-                cb[b] = __builtin_bit_cast(bf16x8_ls, bv);
-            }
-            ls_gram_step<NT, Q0>(acc, a, cb, std::make_integer_sequence<int, PW>{});
-            __builtin_amdgcn_sched_barrier(0);
-        }
+    };
+    const uint32_t *Xf = &X[0][0];
+    fetch(0);
+    // whole tiles, then the ragged one (apart, so that the loop carries the
+    // accumulators in place)
+    int m0 = 0;
+    for (; m0 + kLsTile <= nl; m0 += kLsTile) {
+        build(m0);
+        ls_gram_tile<NT, Q0, PW, GK, false>(acc, Xf, addr, kw, g2, kLsTile);
+    }
+    if (m0 < nl) {
+        build(m0);
+        ls_gram_tile<NT, Q0, PW, GK, true>(acc, Xf, addr, kw, g2, nl - m0);
     }
     // Sum the GK partial tiles of each pair: the four waves put their
     // accumulators (pair u of their group) in LDS, then the waves of a group
     // each add up 4 / GK of the register slots, in wave order.  Tile element
     // (4 (l / 16) + v, l % 16) is register v of lane l.
-    float *buf = reinterpret_cast<float *>(&X[0][0]);   // 4 x 256 floats (the tile: 64 x ls_stride(NT) >= 1088 words)
+    float *buf = reinterpret_cast<float *>(&X[0][0]);   // 4 x 256 floats (kLsRows x kLsBStride >= 1024 words)
     float *out = p.partials + (slab * NP + Q0) * 256;
-    const int wv = tid >> 6;
     for (int u = 0; u < PP; ++u) {
         __syncthreads();   // the matrix reads of the last tile / the previous pair's sums are done
         if (u < PW) {
@@ -288,25 +331,20 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[ls
     }
 }
 
-// Normal equations of one slab of samples: features of 64 samples at a time
-// staged in LDS (rows = samples, ls_stride(NT) floats), then the upper
-// triangle of the real Gram on the matrix cores, FP32 tiles per slab.  One
-// instance per column-tile count NT.
+// Normal equations of one slab of samples: the basis of 64 samples at a time
+// staged in LDS, then the upper triangle of the real Gram on the matrix
+// cores, FP32 tiles per slab.  One instance per column-tile count NT.
 template <int NT>
 __global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
 {
-    static_assert(kLsTile * ls_stride(NT) >= kLsWaves * 256, "LDS tile too small for the final sums");
-    __shared__ uint32_t X[kLsTile][ls_stride(NT)];
-    const int tid = threadIdx.x;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    static_assert(kLsRows * kLsBStride >= kLsWaves * 256, "LDS tile too small for the final sums");
+    __shared__ __align__(16) uint32_t X[kLsRows][kLsBStride];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t slab = blockIdx.x;
     const int64_t row = slab / p.slabs_per_row;
     const int64_t s0 = (slab - row * p.slabs_per_row) * p.slab;
     const float2 *yr = p.y + row * p.ld;
     const float2 *tr = p.t + row * p.ld;
-    const int pad = p.Dp - p.D;
-    if (pad > 0)
-        for (int e = tid; e < kLsTile * pad; e += kBlock) X[e / pad][p.D + e % pad] = 0u;
     const int64_t send = std::min<int64_t>(s0 + p.slab, p.n);
     if constexpr (ls_pair_groups(NT) == 1) {
         ls_gram_wave<NT, 0>(p, X, slab, s0, send, yr, tr);
@@ -318,7 +356,6 @@ __global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
     }
 }
 
-// First level: FP64 sums of the partials of kLsGroup consecutive slabs.
 __global__ void __launch_bounds__(kBlock) ls_reduce1_kernel(const float *__restrict__ partials, int64_t nslabs,
                                                             int64_t E, double *__restrict__ r1)
 {
@@ -663,6 +700,34 @@ static LsWs ls_ws(const LsShape &s, int64_t rows, int64_t n)
     return w;
 }
 
+// Feature f of a sample m (the column order of the real formulation) as a
+// word of the LDS basis rows: row offset L - 1 - k for tap k, then the entry.
+// Branch group g = f / L (main groups first) carries power level j with
+// main_idx[j] == g (or conj_idx[j] == g - n_main); the conjugate branch takes
+// -Im.  Padding columns read the zero word.
+static void ls_offsets(const CoefMap &map, const LsShape &s, int16_t *off)
+{
+    const int H = map.L - 1;
+    int level[2 * kMaxNI];
+    for (int j = 0; j < map.NI; ++j) {
+        if (map.main_idx[j] >= 0) level[map.main_idx[j]] = j;
+        if (map.conj_idx[j] >= 0) level[map.n_main + map.conj_idx[j]] = j;
+    }
+    const int at = H * kLsBStride;   // tap 0
+    for (int f = 0; f < kLsMaxDp; ++f) off[f] = (int16_t)(at + 2 * kLsWZero);
+    for (int f = 0; f < s.K - 1; ++f) {
+        const int g = f / map.L, k = f % map.L;
+        const int j = level[g];
+        const bool conj = g >= map.n_main;
+        const int base = (H - k) * kLsBStride;
+        off[f] = (int16_t)(base + 2 * j);
+        off[s.K + f] = (int16_t)(base + 2 * ((conj ? kLsWNegIm : kLsWIm) + j));
+    }
+    off[s.K - 1] = (int16_t)(at + 2 * kLsWOne);
+    off[2 * s.K] = (int16_t)(at + 2 * kLsWT);
+    off[2 * s.K + 1] = (int16_t)(at + 2 * (kLsWT + 1));
+}
+
 }  // namespace dpd
 
 using namespace dpd;
@@ -727,10 +792,7 @@ DPD_EXPORT dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y,
     p.npairs = s.npairs;
     p.L = map.L;
     p.NI = map.NI;
-    for (int j = 0; j < kMaxNI; ++j) {
-        p.cm[j] = (int16_t)(map.main_idx[j] >= 0 ? map.main_idx[j] * map.L : -1);
-        p.cc[j] = (int16_t)(map.conj_idx[j] >= 0 ? (map.n_main + map.conj_idx[j]) * map.L : -1);
-    }
+    ls_offsets(map, s, p.off);
     if (nslabs >= ((int64_t)1 << 31)) return DPD_EUNSUPPORTED;
     hipLaunchKernelGGL(ls_gram_table()[s.nt - 1], dim3((uint32_t)nslabs), dim3(kBlock), 0, st, p);
     e = hipGetLastError();
