@@ -114,8 +114,8 @@ __device__ __forceinline__ void ls_pack2(float a, float b, uint32_t &wa, uint32_
     const uint32_t hw = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_ls{a, b}, bf16x2_ls));
     const float ha = __uint_as_float(hw << 16), hb = __uint_as_float(hw & 0xffff0000u);
     const uint32_t lw = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_ls{a - ha, b - hb}, bf16x2_ls));
-    wa = (hw & 0xffffu) | (lw << 16);
-    wb = (hw >> 16) | (lw & 0xffff0000u);
+    wa = __builtin_amdgcn_perm(lw, hw, 0x05040100u);   // (hw & 0xffff) | (lw << 16)
+    wb = __builtin_amdgcn_perm(lw, hw, 0x07060302u);   // (hw >> 16) | (lw & 0xffff0000)
 }
 
 // One 8-sample step of the pairs Q0, Q0 + 1, ...: a[b] / c[b] are operand
@@ -224,43 +224,43 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
 #pragma unroll
     for (int b = 0; b < NT; ++b) addr[b] = (8 * kw + g2) * kLsBStride + p.off[16 * b + c];
 
-    // Basis rows r = lane and r = lane + 64 (when below R) of each tile: the
-    // samples (and targets) are loaded one tile ahead, during the previous
-    // tile's matrix phase.  32-bit sample indices relative to the slab start:
-    // nl samples in the slab, inputs valid from index lo on (the row start, or
+    // Basis rows: row r holds sample m0 - H + r of tile m0, so the tile's own
+    // samples are rows H..H+63 (lane l builds row H + l: its sample and its
+    // target are loaded one tile ahead, during the previous tile's matrix
+    // phase) and the H rows before them are rows 64..63+H of the previous
+    // tile, carried over (read at the end of its matrix phase, written after
+    // the barrier).  32-bit sample indices relative to the slab start: nl
+    // samples in the slab, inputs valid from index lo on (the row start, or
     // kMaxL samples back).
     const int H = p.L - 1;
-    const bool two = lane < H;
+    const bool halo = lane < H;
     const bool last = wv == kLsWaves - 1;
     const int lpw = (p.NI + kLsWaves - 1) / kLsWaves;
     const int j0 = wv * lpw, nj = std::min(p.NI - j0, lpw);
+    constexpr int UJ = (kMaxNI + kLsWaves - 1) / kLsWaves;   // levels per wave at most
     const float2 *ys = yr + s0, *ts = tr + s0;
     const int nl = (int)(send - s0);
     const int lo = s0 >= kMaxL ? -kMaxL : (int)-s0;
     // (zeros as literals: a named zero turns the guarded loads into flat
     // loads through a pointer select, with the zero in scratch memory)
-    float2 y0 = make_float2(0.f, 0.f), y1 = y0, t0 = y0, t1 = y0;
+    float2 y0 = make_float2(0.f, 0.f), t0 = y0;
     auto fetch = [&](int m0) {
-        const int q0 = m0 - H + lane, q1 = q0 + 64;
-        y0 = (q0 < nl && q0 >= lo) ? ys[q0] : make_float2(0.f, 0.f);
-        y1 = (two && q1 < nl) ? ys[q1] : make_float2(0.f, 0.f);
-        if (last) {
-            t0 = (lane >= H && q0 < nl) ? ts[q0] : make_float2(0.f, 0.f);
-            t1 = (two && q1 < nl) ? ts[q1] : make_float2(0.f, 0.f);
-        }
+        const int q = m0 + lane;
+        y0 = q < nl ? ys[q] : make_float2(0.f, 0.f);
+        if (last) t0 = q < nl ? ts[q] : make_float2(0.f, 0.f);
     };
-    // psi_j for j in [j0, j0 + nj) of sample y into row x (nj <= 2 uniform)
     auto put = [](uint32_t *x, int e, uint32_t w) {
         x[2 * e] = w;
         x[2 * e + 1] = w;
     };
+    // psi_j for j in [j0, j0 + nj) of sample y into row x (nj <= UJ uniform)
     auto levels = [&](uint32_t *x, float2 y) {
         const float vx = p.y_scale * y.x, vy = p.y_scale * y.y;
         const float s2 = __builtin_fmaf(vx, vx, vy * vy);
         float pw = 1.f;
         for (int e = 0; e < j0; ++e) pw *= s2;
 #pragma unroll
-        for (int u = 0; u < (kMaxNI + kLsWaves - 1) / kLsWaves; ++u) {
+        for (int u = 0; u < UJ; ++u) {
             if (u < nj) {
                 uint32_t wa, wb;
                 ls_pack2(pw * vx, pw * vy, wa, wb);
@@ -271,27 +271,52 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
             }
         }
     };
-    auto target = [&](uint32_t *x, float2 t, bool in) {
-        uint32_t ta, tb;
-        ls_pack2(t.x, t.y, ta, tb);
-        put(x, kLsWOne, in ? ls_pack(1.f) : 0u);
-        put(x, kLsWZero, 0u);
-        put(x, kLsWT, ta);
-        put(x, kLsWT + 1, tb);
+    // the carried rows: this wave's level entries of rows 64..63+H
+    uint2 hv[3 * UJ];
+    auto halo_read = [&]() {
+        const uint2 *x = reinterpret_cast<const uint2 *>(X[64 + lane]);
+#pragma unroll
+        for (int u = 0; u < UJ; ++u) {
+            if (u < nj) {
+                hv[3 * u] = x[j0 + u];
+                hv[3 * u + 1] = x[kLsWIm + j0 + u];
+                hv[3 * u + 2] = x[kLsWNegIm + j0 + u];
+            }
+        }
+    };
+    auto halo_write = [&]() {
+        uint2 *x = reinterpret_cast<uint2 *>(X[lane]);
+#pragma unroll
+        for (int u = 0; u < UJ; ++u) {
+            if (u < nj) {
+                x[j0 + u] = hv[3 * u];
+                x[kLsWIm + j0 + u] = hv[3 * u + 1];
+                x[kLsWNegIm + j0 + u] = hv[3 * u + 2];
+            }
+        }
     };
     auto build = [&](int m0) {
         __syncthreads();   // the previous tile's matrix-core reads are done
-        levels(X[lane], y0);
-        if (two) levels(X[lane + 64], y1);
+        if (m0 > 0 && halo) halo_write();
+        uint32_t *x = X[H + lane];
+        levels(x, y0);
         if (last) {
-            // row r holds sample m0 - H + r; tile samples are rows H..H+63
-            target(X[lane], t0, lane >= H && m0 - H + lane < nl);
-            if (two) target(X[lane + 64], t1, m0 + 64 - H + lane < nl);
+            uint32_t ta, tb;
+            ls_pack2(t0.x, t0.y, ta, tb);
+            put(x, kLsWOne, m0 + lane < nl ? ls_pack(1.f) : 0u);
+            put(x, kLsWZero, 0u);
+            put(x, kLsWT, ta);
+            put(x, kLsWT + 1, tb);
         }
         __syncthreads();
         if (m0 + kLsTile < nl) fetch(m0 + kLsTile);
     };
     const uint32_t *Xf = &X[0][0];
+    // the rows before the slab's first tile (zero before the row start)
+    if (halo) {
+        const int q = lane - H;
+        levels(X[lane], q >= lo ? ys[q] : make_float2(0.f, 0.f));
+    }
     fetch(0);
     // whole tiles, then the ragged one (apart, so that the loop carries the
     // accumulators in place)
@@ -299,6 +324,7 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
     for (; m0 + kLsTile <= nl; m0 += kLsTile) {
         build(m0);
         ls_gram_tile<NT, Q0, PW, GK, false>(acc, Xf, addr, kw, g2, kLsTile);
+        if (halo && m0 + kLsTile < nl) halo_read();
     }
     if (m0 < nl) {
         build(m0);

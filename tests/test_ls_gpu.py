@@ -72,6 +72,8 @@ CASES = [  # (main orders, conj orders, L, n)
     ([1, 3, 5, 7, 9], [1, 3, 5], 5, 3000),      # K = 41: 6 x 6 tiles
     ([1, 3, 5, 7, 9, 11, 13], [1, 3, 5, 7, 9, 11, 13], 4, 6000),  # K = 57: 8 x 8 tiles, two pair groups
     ([1, 3, 5, 7, 9, 11, 13, 15], [1, 3, 5], 8, 2500),  # K = 89: 12 x 12 tiles, the largest basis
+    ([1, 3], [1], 16, 3000),                    # the most taps: 15 rows carried between tiles
+    ([1, 5, 9], [3, 7], 3, 2000),               # orders with gaps, levels split between the branches
 ]
 
 
