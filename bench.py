@@ -416,7 +416,7 @@ def leg_ls(torch, dpd, signals, reps=5):
         ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
         us = autotune.time_us(lambda: dpd.dpd_ls_normal(plan.handle, st, y.data_ptr(), t.data_ptr(), 1, n, n, 1.0,
                                                         ws.data_ptr(), wsb, A.data_ptr(), b.data_ptr()),
-                              warmup=3, iters=reps)
+                              warmup=20, iters=4 * reps)   # steady clocks: ~30 ms of work at 2^24
         out["normal_2^%d_us" % lg] = round(us, 1)
         out["normal_2^%d_useful_tflops" % lg] = round(useful * n / (us * 1e-6) / 1e12, 2)
         out["normal_2^%d_mfma_bf16_tflops" % lg] = round(issued * n / (us * 1e-6) / 1e12, 2)

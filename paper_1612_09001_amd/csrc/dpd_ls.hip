@@ -157,10 +157,11 @@ constexpr int kLsRows = kLsTile + kMaxL - 1;
 // scheduling barrier per step keeps one step's operands in registers.  With
 // MASK the samples at or past vt (the end of the slab) contribute nothing:
 // their row-side operands are zeroed.
-template <int NT, int Q0, int PW, int GK, bool MASK>
+template <int NT, int Q0, int PW, int GK, bool MASK, typename Mid>
 __device__ __forceinline__ void ls_gram_tile(v4f_ls *acc, const uint32_t *Xf, const int *addr, int kw, int g2,
-                                             int vt)
+                                             int vt, Mid mid)
 {
+    mid();   // the next tile's basis, into the other buffer
 #pragma unroll
     for (int i = 0; i < kLsTile / 8 / GK; ++i) {
         const int row = 8 * GK * i;   // step kw + GK i, relative to the wave's first step
@@ -225,13 +226,14 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
     for (int b = 0; b < NT; ++b) addr[b] = (8 * kw + g2) * kLsBStride + p.off[16 * b + c];
 
     // Basis rows: row r holds sample m0 - H + r of tile m0, so the tile's own
-    // samples are rows H..H+63 (lane l builds row H + l: its sample and its
-    // target are loaded one tile ahead, during the previous tile's matrix
-    // phase) and the H rows before them are rows 64..63+H of the previous
-    // tile, carried over (read at the end of its matrix phase, written after
-    // the barrier).  32-bit sample indices relative to the slab start: nl
-    // samples in the slab, inputs valid from index lo on (the row start, or
-    // kMaxL samples back).
+    // samples are rows H..H+63 (lane l builds row H + l) and the H rows before
+    // them are rows 64..63+H of the previous tile.  Two LDS buffers: tile
+    // t + 1 is built into one (its carried rows copied from tile t's) between
+    // the matrix steps of tile t on the other, one barrier per tile.  A lane's
+    // sample and target are loaded two tiles ahead of their matrix phase.
+    // 32-bit sample indices relative to the slab start: nl samples in the
+    // slab, inputs valid from index lo on (the row start, or kMaxL samples
+    // back).
     const int H = p.L - 1;
     const bool halo = lane < H;
     const bool last = wv == kLsWaves - 1;
@@ -271,34 +273,21 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
             }
         }
     };
-    // the carried rows: this wave's level entries of rows 64..63+H
-    uint2 hv[3 * UJ];
-    auto halo_read = [&]() {
-        const uint2 *x = reinterpret_cast<const uint2 *>(X[64 + lane]);
+    // tile m0 into buffer B (the carried rows from buffer B ^ 1 unless first)
+    auto build = [&](int m0, uint32_t (*B)[kLsBStride], const uint32_t (*P)[kLsBStride]) {
+        if (m0 > 0 && halo) {
+            const uint2 *src = reinterpret_cast<const uint2 *>(P[64 + lane]);
+            uint2 *dst = reinterpret_cast<uint2 *>(B[lane]);
 #pragma unroll
-        for (int u = 0; u < UJ; ++u) {
-            if (u < nj) {
-                hv[3 * u] = x[j0 + u];
-                hv[3 * u + 1] = x[kLsWIm + j0 + u];
-                hv[3 * u + 2] = x[kLsWNegIm + j0 + u];
+            for (int u = 0; u < UJ; ++u) {
+                if (u < nj) {
+                    dst[j0 + u] = src[j0 + u];
+                    dst[kLsWIm + j0 + u] = src[kLsWIm + j0 + u];
+                    dst[kLsWNegIm + j0 + u] = src[kLsWNegIm + j0 + u];
+                }
             }
         }
-    };
-    auto halo_write = [&]() {
-        uint2 *x = reinterpret_cast<uint2 *>(X[lane]);
-#pragma unroll
-        for (int u = 0; u < UJ; ++u) {
-            if (u < nj) {
-                x[j0 + u] = hv[3 * u];
-                x[kLsWIm + j0 + u] = hv[3 * u + 1];
-                x[kLsWNegIm + j0 + u] = hv[3 * u + 2];
-            }
-        }
-    };
-    auto build = [&](int m0) {
-        __syncthreads();   // the previous tile's matrix-core reads are done
-        if (m0 > 0 && halo) halo_write();
-        uint32_t *x = X[H + lane];
+        uint32_t *x = B[H + lane];
         levels(x, y0);
         if (last) {
             uint32_t ta, tb;
@@ -308,28 +297,30 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
             put(x, kLsWT, ta);
             put(x, kLsWT + 1, tb);
         }
-        __syncthreads();
         if (m0 + kLsTile < nl) fetch(m0 + kLsTile);
     };
-    const uint32_t *Xf = &X[0][0];
     // the rows before the slab's first tile (zero before the row start)
     if (halo) {
         const int q = lane - H;
         levels(X[lane], q >= lo ? ys[q] : make_float2(0.f, 0.f));
     }
     fetch(0);
+    build(0, X, X);
+    __syncthreads();
     // whole tiles, then the ragged one (apart, so that the loop carries the
     // accumulators in place)
-    int m0 = 0;
-    for (; m0 + kLsTile <= nl; m0 += kLsTile) {
-        build(m0);
-        ls_gram_tile<NT, Q0, PW, GK, false>(acc, Xf, addr, kw, g2, kLsTile);
-        if (halo && m0 + kLsTile < nl) halo_read();
+    int m0 = 0, cur = 0;
+    for (; m0 + kLsTile <= nl; m0 += kLsTile, cur ^= 1) {
+        uint32_t(*B)[kLsBStride] = X + cur * kLsRows;
+        uint32_t(*N)[kLsBStride] = X + (cur ^ 1) * kLsRows;
+        const int mn = m0 + kLsTile;
+        ls_gram_tile<NT, Q0, PW, GK, false>(acc, &B[0][0], addr, kw, g2, kLsTile, [&]() {
+            if (mn < nl) build(mn, N, B);
+        });
+        __syncthreads();   // tile m0's reads and tile m0 + 64's writes are done
     }
-    if (m0 < nl) {
-        build(m0);
-        ls_gram_tile<NT, Q0, PW, GK, true>(acc, Xf, addr, kw, g2, nl - m0);
-    }
+    if (m0 < nl)
+        ls_gram_tile<NT, Q0, PW, GK, true>(acc, &X[cur * kLsRows][0], addr, kw, g2, nl - m0, []() {});
     // Sum the GK partial tiles of each pair: the four waves put their
     // accumulators (pair u of their group) in LDS, then the waves of a group
     // each add up 4 / GK of the register slots, in wave order.  Tile element
@@ -364,7 +355,7 @@ template <int NT>
 __global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
 {
     static_assert(kLsRows * kLsBStride >= kLsWaves * 256, "LDS tile too small for the final sums");
-    __shared__ __align__(16) uint32_t X[kLsRows][kLsBStride];
+    __shared__ __align__(16) uint32_t X[2 * kLsRows][kLsBStride];   // two tile buffers
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t slab = blockIdx.x;
     const int64_t row = slab / p.slabs_per_row;
