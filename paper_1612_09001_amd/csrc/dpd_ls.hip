@@ -154,9 +154,11 @@ constexpr int kLsRows = kLsTile + kMaxL - 1;
 // One 64-sample tile of the matrix phase.  Lane l feeds row / column l % 16
 // and samples 2 (l / 16), 2 (l / 16) + 1 of each 8-sample step (four slots
 // each); a step's operand blocks are read once and feed every pair; a
-// scheduling barrier per step keeps one step's operands in registers.  With
-// MASK the samples at or past vt (the end of the slab) contribute nothing:
-// their row-side operands are zeroed.
+// scheduling barrier per step keeps one step's operands in registers.  mid()
+// runs first (the next tile's basis goes into the other LDS buffer: kept out
+// of the matrix steps, where its branches would make the accumulators move
+// between registers).  With MASK the samples at or past vt (the end of the
+// slab) contribute nothing: their row-side operands are zeroed.
 template <int NT, int Q0, int PW, int GK, bool MASK, typename Mid>
 __device__ __forceinline__ void ls_gram_tile(v4f_ls *acc, const uint32_t *Xf, const int *addr, int kw, int g2,
                                              int vt, Mid mid)
@@ -194,9 +196,10 @@ __device__ __forceinline__ void ls_gram_tile(v4f_ls *acc, const uint32_t *Xf, co
 // them) accumulate the tile pairs [G PP, (G + 1) PP) of the row-major upper
 // triangle, each over every GK-th 8-sample step of each 64-sample tile, so
 // a step loads each 16-column operand block once for all of its pairs.  All
-// four waves build the basis rows of each tile together (barriers): wave w
-// the power levels [w lpw, (w + 1) lpw), the last wave also the constant and
-// target words.  At the end the GK partial tiles of each pair are summed
+// four waves build the basis rows of each tile together, one tile ahead into
+// the other of two LDS buffers (one barrier per tile): wave w the power levels
+// [w lpw, (w + 1) lpw), the last wave also the constant and target words.
+// At the end the GK partial tiles of each pair are summed
 // through LDS (fixed order) and written out.  The pair list is a compile-time
 // constant: the matrix loop has no conditionals (a guarded accumulation
 // becomes a branch whose merge copies every accumulator) and every wave runs
@@ -349,7 +352,7 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
 }
 
 // Normal equations of one slab of samples: the basis of 64 samples at a time
-// staged in LDS, then the upper triangle of the real Gram on the matrix
+// staged in LDS (two buffers), then the upper triangle of the real Gram on the matrix
 // cores, FP32 tiles per slab.  One instance per column-tile count NT.
 template <int NT>
 __global__ void __launch_bounds__(kBlock) ls_gram_kernel(LsParams p)
