@@ -51,6 +51,13 @@ constexpr int kLsMaxNt = kLsMaxDp / 16;
 constexpr int kLsWaves = kBlock / 64;
 constexpr int kLsGroup = 64;        // slabs per first-level FP64 sum
 
+// Entries of a basis row (roles): Re psi_j, Im psi_j, -Im psi_j for each
+// power level j, the constant, a zero and the target (Re, Im).
+constexpr int kLsRIm = kMaxNI, kLsRNegIm = 2 * kMaxNI;
+constexpr int kLsROne = 3 * kMaxNI, kLsRZero = kLsROne + 1, kLsRT = kLsROne + 2;
+constexpr int kLsRoles = kLsRT + 2;
+static_assert(kLsRoles <= 32 && kLsRoles <= 3 * kMaxNI + 5, "plan slot table too small");
+
 struct LsParams {
     const float2 *y;        // basis input, rows x ld
     const float2 *t;        // target, same layout
@@ -62,6 +69,7 @@ struct LsParams {
     int K, D, Dp, nt, npairs;
     int L, NI;
     int16_t off[kLsMaxDp];  // LDS word of feature f relative to the basis row of the sample
+    int8_t slot[kLsRoles];  // LDS row slot of each basis entry
 };
 
 // Tile pair q of the upper triangle, row-major over (I <= J).
@@ -119,8 +127,8 @@ __device__ __forceinline__ void ls_pack2(float a, float b, uint32_t &wa, uint32_
 }
 
 // One 8-sample step of the pairs Q0, Q0 + 1, ...: a[b] / c[b] are operand
-// block b as (hi, lo, hi, lo) per sample and as (hi, lo, lo, hi), so every
-// sample contributes hi hi' + lo lo' + hi lo' + lo hi'.  The blocks of each
+// block b as (hi, lo, hi, lo) per sample and as (hi, hi, lo, lo), so every
+// sample contributes hi hi' + lo hi' + hi lo' + lo lo'.  The blocks of each
 // pair are compile-time constants (forced).
 template <int NT, int Q0, int... U>
 __device__ __forceinline__ void ls_gram_step(v4f_ls *acc, const bf16x8_ls *a, const bf16x8_ls *c,
@@ -144,11 +152,11 @@ constexpr int ls_pair_groups(int nt) { return nt * (nt + 1) / 2 * 4 <= 128 ? 1 :
 // one 64-bit read per sample gives the row-side operand).  Row m of Psi
 // repeats the rows of samples m, m-1, ..., m-L+1 (Eq. 2 is Toeplitz in the
 // taps), so each Gram column f reads the word off[f] = (L - 1 - k) stride +
-// 2 entry(f) relative to row m.
-constexpr int kLsBEntries = 3 * kMaxNI + 5;        // 3 NI + 4 entries per row, odd
+// 2 slot(f) relative to row m.  The slot of each entry in a row is chosen per
+// basis layout on the host (ls_layout) to spread the matrix phase's reads over
+// the LDS banks.
+constexpr int kLsBEntries = 3 * kMaxNI + 5;        // slots per row (odd: rows start on rotating banks)
 constexpr int kLsBStride = 2 * kLsBEntries;        // words per row
-constexpr int kLsWIm = kMaxNI, kLsWNegIm = 2 * kMaxNI;
-constexpr int kLsWOne = 3 * kMaxNI, kLsWZero = kLsWOne + 1, kLsWT = kLsWOne + 2;
 constexpr int kLsRows = kLsTile + kMaxL - 1;
 
 // One 64-sample tile of the matrix phase.  Lane l feeds row / column l % 16
@@ -178,12 +186,13 @@ __device__ __forceinline__ void ls_gram_tile(v4f_ls *acc, const uint32_t *Xf, co
         for (int b = 0; b < NT; ++b) {
             const uint2 p0 = *reinterpret_cast<const uint2 *>(Xf + addr[b] + row * kLsBStride);
             const uint2 p1 = *reinterpret_cast<const uint2 *>(Xf + addr[b] + (row + 1) * kLsBStride);
-            // (hi, lo) twice against (hi', lo') then (lo', hi'): the two slot
-            // pairs of a sample give hi hi' + lo lo' and hi lo' + lo hi'
+            // (hi, lo, hi, lo) against (hi', hi', lo', lo'): the four slots of a
+            // sample give hi hi' + lo hi' + hi lo' + lo lo' (the column side
+            // by byte permutes written straight into the operand)
             const u32x4_ls av = MASK ? u32x4_ls{ok0 ? p0.x : 0u, ok0 ? p0.y : 0u, ok1 ? p1.x : 0u, ok1 ? p1.y : 0u}
                                      : u32x4_ls{p0.x, p0.y, p1.x, p1.y};
-            const u32x4_ls bv = {p0.x, __builtin_amdgcn_alignbit(p0.y, p0.y, 16), p1.x,
-                                 __builtin_amdgcn_alignbit(p1.y, p1.y, 16)};
+            const u32x4_ls bv = {__builtin_amdgcn_perm(p0.x, p0.x, 0x01000100u), __builtin_amdgcn_perm(p0.y, p0.y, 0x03020302u),
+                                 __builtin_amdgcn_perm(p1.x, p1.x, 0x01000100u), __builtin_amdgcn_perm(p1.y, p1.y, 0x03020302u)};
             a[b] = __builtin_bit_cast(bf16x8_ls, av);
             cb[b] = __builtin_bit_cast(bf16x8_ls, bv);
         }
@@ -243,6 +252,15 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
     const int lpw = (p.NI + kLsWaves - 1) / kLsWaves;
     const int j0 = wv * lpw, nj = std::min(p.NI - j0, lpw);
     constexpr int UJ = (kMaxNI + kLsWaves - 1) / kLsWaves;   // levels per wave at most
+    // the row slots of this wave's level entries (Re, Im, -Im)
+    int sre[UJ], sim[UJ], sng[UJ];
+#pragma unroll
+    for (int u = 0; u < UJ; ++u) {
+        const int j = (j0 + u) & (kMaxNI - 1);   // in range also where u >= nj (unused there)
+        sre[u] = p.slot[j];
+        sim[u] = p.slot[kLsRIm + j];
+        sng[u] = p.slot[kLsRNegIm + j];
+    }
     const float2 *ys = yr + s0, *ts = tr + s0;
     const int nl = (int)(send - s0);
     const int lo = s0 >= kMaxL ? -kMaxL : (int)-s0;
@@ -269,9 +287,9 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
             if (u < nj) {
                 uint32_t wa, wb;
                 ls_pack2(pw * vx, pw * vy, wa, wb);
-                put(x, j0 + u, wa);
-                put(x, kLsWIm + j0 + u, wb);
-                put(x, kLsWNegIm + j0 + u, wb ^ 0x80008000u);   // -b: both parts negated exactly
+                put(x, sre[u], wa);
+                put(x, sim[u], wb);
+                put(x, sng[u], wb ^ 0x80008000u);   // -b: both parts negated exactly
                 pw *= s2;
             }
         }
@@ -284,9 +302,9 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
 #pragma unroll
             for (int u = 0; u < UJ; ++u) {
                 if (u < nj) {
-                    dst[j0 + u] = src[j0 + u];
-                    dst[kLsWIm + j0 + u] = src[kLsWIm + j0 + u];
-                    dst[kLsWNegIm + j0 + u] = src[kLsWNegIm + j0 + u];
+                    dst[sre[u]] = src[sre[u]];
+                    dst[sim[u]] = src[sim[u]];
+                    dst[sng[u]] = src[sng[u]];
                 }
             }
         }
@@ -295,10 +313,10 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
         if (last) {
             uint32_t ta, tb;
             ls_pack2(t0.x, t0.y, ta, tb);
-            put(x, kLsWOne, m0 + lane < nl ? ls_pack(1.f) : 0u);
-            put(x, kLsWZero, 0u);
-            put(x, kLsWT, ta);
-            put(x, kLsWT + 1, tb);
+            put(x, p.slot[kLsROne], m0 + lane < nl ? ls_pack(1.f) : 0u);
+            put(x, p.slot[kLsRZero], 0u);
+            put(x, p.slot[kLsRT], ta);
+            put(x, p.slot[kLsRT + 1], tb);
         }
         if (m0 + kLsTile < nl) fetch(m0 + kLsTile);
     };
@@ -720,32 +738,94 @@ static LsWs ls_ws(const LsShape &s, int64_t rows, int64_t n)
     return w;
 }
 
-// Feature f of a sample m (the column order of the real formulation) as a
-// word of the LDS basis rows: row offset L - 1 - k for tap k, then the entry.
-// Branch group g = f / L (main groups first) carries power level j with
+// Role and tap of feature f (the column order of the real formulation):
+// branch group g = f / L (main groups first) carries power level j with
 // main_idx[j] == g (or conj_idx[j] == g - n_main); the conjugate branch takes
-// -Im.  Padding columns read the zero word.
-static void ls_offsets(const CoefMap &map, const LsShape &s, int16_t *off)
+// -Im.  Padding columns read the zero entry (tap 0).
+static void ls_columns(const CoefMap &map, const LsShape &s, int *role, int *tap)
 {
-    const int H = map.L - 1;
     int level[2 * kMaxNI];
     for (int j = 0; j < map.NI; ++j) {
         if (map.main_idx[j] >= 0) level[map.main_idx[j]] = j;
         if (map.conj_idx[j] >= 0) level[map.n_main + map.conj_idx[j]] = j;
     }
-    const int at = H * kLsBStride;   // tap 0
-    for (int f = 0; f < kLsMaxDp; ++f) off[f] = (int16_t)(at + 2 * kLsWZero);
+    for (int f = 0; f < s.Dp; ++f) {
+        role[f] = kLsRZero;
+        tap[f] = 0;
+    }
     for (int f = 0; f < s.K - 1; ++f) {
         const int g = f / map.L, k = f % map.L;
         const int j = level[g];
-        const bool conj = g >= map.n_main;
-        const int base = (H - k) * kLsBStride;
-        off[f] = (int16_t)(base + 2 * j);
-        off[s.K + f] = (int16_t)(base + 2 * ((conj ? kLsWNegIm : kLsWIm) + j));
+        role[f] = j;
+        role[s.K + f] = (g >= map.n_main ? kLsRNegIm : kLsRIm) + j;
+        tap[f] = tap[s.K + f] = k;
     }
-    off[s.K - 1] = (int16_t)(at + 2 * kLsWOne);
-    off[2 * s.K] = (int16_t)(at + 2 * kLsWT);
-    off[2 * s.K + 1] = (int16_t)(at + 2 * (kLsWT + 1));
+    role[s.K - 1] = kLsROne;
+    role[2 * s.K] = kLsRT;
+    role[2 * s.K + 1] = kLsRT + 1;
+}
+
+// Feature f of a sample as a word of the LDS basis rows: row offset L - 1 - k
+// for tap k, then the slot of its entry.
+static void ls_offsets(const CoefMap &map, const LsShape &s, const int8_t *slot, int16_t *off)
+{
+    int role[kLsMaxDp], tap[kLsMaxDp];
+    ls_columns(map, s, role, tap);
+    for (int f = 0; f < kLsMaxDp; ++f) off[f] = (int16_t)(2 * ((map.L - 1) * kLsBEntries + slot[kLsRZero]));
+    for (int f = 0; f < s.Dp; ++f) off[f] = (int16_t)(2 * ((map.L - 1 - tap[f]) * kLsBEntries + slot[role[f]]));
+}
+
+// Slots of the basis entries in an LDS row for one basis layout.  The matrix
+// phase reads, per 16-column operand block, 16 entries at once (one per lane,
+// rows shifted by each column's tap); a 64-bit LDS read serves 16 lanes per
+// cycle over 32 four-byte banks, so distinct entries whose 8-byte units fall
+// on the same bank pair (unit mod 16) take a cycle each.  A short
+// deterministic local search over the slots minimizes the summed worst
+// bank-pair load of the blocks (the odd row length keeps the row-per-lane
+// writes conflict-free for any order).
+void ls_layout(const CoefMap &map, int8_t *slot)
+{
+    for (int r = 0; r < kLsRoles; ++r) slot[r] = (int8_t)r;
+    const LsShape s = ls_shape(map);
+    if (s.Dp > kLsMaxDp) return;
+    int role[kLsMaxDp], tap[kLsMaxDp];
+    ls_columns(map, s, role, tap);
+    auto cost = [&]() {
+        int total = 0;
+        for (int b = 0; b < s.nt; ++b) {
+            int unit[16], load[16] = {0}, worst = 0;
+            for (int c = 0; c < 16; ++c) {
+                const int f = 16 * b + c;
+                unit[c] = (map.L - 1 - tap[f]) * kLsBEntries + slot[role[f]];
+                bool seen = false;
+                for (int d = 0; d < c; ++d) seen |= unit[d] == unit[c];
+                if (!seen) worst = std::max(worst, ++load[unit[c] & 15]);
+            }
+            total += worst;
+        }
+        return total;
+    };
+    int best = cost();
+    uint32_t rng = 0x9e3779b9u;
+    for (int it = 0; it < 4000 && best > s.nt; ++it) {
+        rng = rng * 1664525u + 1013904223u;
+        const int r = (int)((rng >> 8) % kLsRoles);
+        rng = rng * 1664525u + 1013904223u;
+        const int t = (int)((rng >> 8) % kLsBEntries);
+        int other = -1;
+        for (int q = 0; q < kLsRoles; ++q)
+            if (slot[q] == t) other = q;
+        const int8_t was = slot[r];
+        slot[r] = (int8_t)t;
+        if (other >= 0) slot[other] = was;
+        const int c = cost();
+        if (c <= best) {
+            best = c;
+        } else {
+            if (other >= 0) slot[other] = (int8_t)t;
+            slot[r] = was;
+        }
+    }
 }
 
 }  // namespace dpd
@@ -812,7 +892,8 @@ DPD_EXPORT dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y,
     p.npairs = s.npairs;
     p.L = map.L;
     p.NI = map.NI;
-    ls_offsets(map, s, p.off);
+    std::copy(plan->ls_slot, plan->ls_slot + kLsRoles, p.slot);
+    ls_offsets(map, s, p.slot, p.off);
     if (nslabs >= ((int64_t)1 << 31)) return DPD_EUNSUPPORTED;
     hipLaunchKernelGGL(ls_gram_table()[s.nt - 1], dim3((uint32_t)nslabs), dim3(kBlock), 0, st, p);
     e = hipGetLastError();

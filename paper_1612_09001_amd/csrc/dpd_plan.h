@@ -14,6 +14,7 @@ struct dpd_plan {
     dpd_tune tune;
     std::vector<float> raw;      // host copy of the 2K coefficient floats
     float *d_table = nullptr;    // precombined table (device)
+    int8_t ls_slot[32] = {};     // least squares: LDS row slot of each basis entry
 };
 
 namespace dpd {
@@ -28,5 +29,6 @@ dpd_status run_forward(const CoefMap &map, const dpd_tune &tune, const float *M,
 dpd_status check_io(const void *in, const void *out, int64_t rows, int64_t n, int64_t ld);
 dpd_tune default_tune();
 bool valid_tune(const dpd_tune &t);
+void ls_layout(const CoefMap &map, int8_t *slot);
 
 }  // namespace dpd
