@@ -312,7 +312,6 @@ DPD_EXPORT dpd_status dpd_create(const int32_t *main_orders, int32_t n_main, con
     if (p == nullptr) return DPD_ENOMEM;
     p->map = map;
     p->K = (n_main + n_conj) * L + 1;
-    ls_layout(map, p->ls_slot);
     p->tune = default_tune();
     p->raw.assign(coeffs_host, coeffs_host + 2 * p->K);
     hipError_t e = hipGetDevice(&p->device);

@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cmath>
 #include <type_traits>
 #include <utility>
@@ -892,6 +893,7 @@ DPD_EXPORT dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y,
     p.npairs = s.npairs;
     p.L = map.L;
     p.NI = map.NI;
+    std::call_once(plan->ls_once, [plan]() { ls_layout(plan->map, plan->ls_slot); });
     std::copy(plan->ls_slot, plan->ls_slot + kLsRoles, p.slot);
     ls_offsets(map, s, p.slot, p.off);
     if (nslabs >= ((int64_t)1 << 31)) return DPD_EUNSUPPORTED;

@@ -2,6 +2,7 @@
 // the host translation units of libdpd.
 #pragma once
 
+#include <mutex>
 #include <vector>
 
 #include "dpd.h"
@@ -14,7 +15,8 @@ struct dpd_plan {
     dpd_tune tune;
     std::vector<float> raw;      // host copy of the 2K coefficient floats
     float *d_table = nullptr;    // precombined table (device)
-    int8_t ls_slot[32] = {};     // least squares: LDS row slot of each basis entry
+    int8_t ls_slot[32] = {};     // least squares: LDS row slot of each basis entry,
+    std::once_flag ls_once;      // chosen on the first least-squares call
 };
 
 namespace dpd {
