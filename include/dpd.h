@@ -268,7 +268,10 @@ dpd_status dpd_cascade_backward(const dpd_plan *A, const dpd_plan *B, void *stre
  *   accumulated in FP32 over slabs of 1024 to 4096 samples (the size
  *   depends only on rows, n and the device's CU count), the slabs summed in
  *   FP64 in a fixed order: deterministic.  Allocates nothing, does not
- *   synchronize; rows * n == 0 gives A = 0, b = 0. */
+ *   synchronize; rows * n == 0 gives A = 0, b = 0.  The first call on a plan
+ *   also picks the order of the basis entries in the kernel's shared-memory
+ *   rows (host work, once per plan, a few milliseconds at most; safe when
+ *   several threads make the first call together). */
 dpd_status dpd_ls_ws_size(const dpd_plan *plan, int64_t rows, int64_t n, size_t *bytes);
 dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y, const void *t, int64_t rows,
                          int64_t n, int64_t ld, float y_scale, void *ws, size_t ws_bytes, void *A, void *b);
