@@ -208,9 +208,9 @@ __device__ __forceinline__ void ls_gram_tile(v4f_ls *acc, const uint32_t *Xf, co
 // a step loads each 16-column operand block once for all of its pairs.  All
 // four waves build the basis rows of each tile together, one tile ahead into
 // the other of two LDS buffers (one barrier per tile): wave w the power levels
-// [w lpw, (w + 1) lpw), the last wave also the constant and target words.
-// At the end the GK partial tiles of each pair are summed
-// through LDS (fixed order) and written out.  The pair list is a compile-time
+// [w lpw, (w + 1) lpw), the last wave also the constant and target words.  At
+// the end the GK partial tiles of each pair are summed through LDS (fixed
+// order) and written out.  The pair list is a compile-time
 // constant: the matrix loop has no conditionals (a guarded accumulation
 // becomes a branch whose merge copies every accumulator) and every wave runs
 // the same code.
@@ -241,9 +241,10 @@ __device__ __forceinline__ void ls_gram_wave(const LsParams &p, uint32_t (*X)[kL
     // Basis rows: row r holds sample m0 - H + r of tile m0, so the tile's own
     // samples are rows H..H+63 (lane l builds row H + l) and the H rows before
     // them are rows 64..63+H of the previous tile.  Two LDS buffers: tile
-    // t + 1 is built into one (its carried rows copied from tile t's) between
-    // the matrix steps of tile t on the other, one barrier per tile.  A lane's
-    // sample and target are loaded two tiles ahead of their matrix phase.
+    // t + 1 is built into one (its carried rows copied from tile t's) just
+    // before the matrix steps of tile t on the other, one barrier per tile.  A
+    // lane's sample and target are loaded two tiles ahead of their matrix
+    // phase.
     // 32-bit sample indices relative to the slab start: nl samples in the
     // slab, inputs valid from index lo on (the row start, or kMaxL samples
     // back).
