@@ -478,6 +478,82 @@ __device__ __forceinline__ double ls_bcast(double v, int src)
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// L y = b, then L^H h = y on the factor F (column-major at stride ld, the
+// diagonal in place): one wave, lane l holding rows l, l + 64, ... (R of them)
+// in registers; h in complex64, info = 0.
+template <int R>
+__device__ __forceinline__ void ls_substitute(const double2 *F, int ld, const double2 *__restrict__ b, int K,
+                                              float2 *__restrict__ h, int32_t *__restrict__ info, int lane)
+{
+    int rc[R];   // owned rows clamped into the matrix (loads only)
+#pragma unroll
+    for (int t = 0; t < R; ++t) rc[t] = min(lane + 64 * t, K - 1);
+    double invd[R];   // 1 / L[r][r] of the owned rows
+#pragma unroll
+    for (int t = 0; t < R; ++t) invd[t] = 1.0 / F[rc[t] * ld + rc[t]].x;
+    double2 y[R], f[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int r = lane + 64 * t;
+        y[t] = r < K ? b[r] : make_double2(0.0, 0.0);
+        f[t] = F[rc[t]];   // column 0
+    }
+    for (int j = 0; j < K; ++j) {
+        double2 fn[R];
+        const int jn = min(j + 1, K - 1);
+#pragma unroll
+        for (int t = 0; t < R; ++t) fn[t] = F[jn * ld + rc[t]];   // L[r][j+1]
+        double2 mine = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+            if (t == (j >> 6)) mine = make_double2(y[t].x * invd[t], y[t].y * invd[t]);
+        const double2 yj = make_double2(ls_bcast(mine.x, j & 63), ls_bcast(mine.y, j & 63));
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int r = lane + 64 * t;
+            if (r == j) {
+                y[t] = yj;
+            } else if (r > j) {
+                // y_r -= L[r][j] y_j
+                y[t].x -= f[t].x * yj.x - f[t].y * yj.y;
+                y[t].y -= f[t].x * yj.y + f[t].y * yj.x;
+            }
+            f[t] = fn[t];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) f[t] = F[rc[t] * ld + (K - 1)];   // L[K-1][r]
+    for (int j = K - 1; j >= 0; --j) {
+        double2 fn[R];
+        const int jn = max(j - 1, 0);
+#pragma unroll
+        for (int t = 0; t < R; ++t) fn[t] = F[rc[t] * ld + jn];   // L[j-1][r]
+        double2 mine = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < R; ++t)
+            if (t == (j >> 6)) mine = make_double2(y[t].x * invd[t], y[t].y * invd[t]);
+        const double2 hj = make_double2(ls_bcast(mine.x, j & 63), ls_bcast(mine.y, j & 63));
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const int r = lane + 64 * t;
+            if (r == j) {
+                y[t] = hj;
+            } else if (r < j) {
+                // y_r -= conj(L[j][r]) h_j
+                y[t].x -= f[t].x * hj.x + f[t].y * hj.y;
+                y[t].y -= f[t].x * hj.y - f[t].y * hj.x;
+            }
+            f[t] = fn[t];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        const int r = lane + 64 * t;
+        if (r < K) h[r] = make_float2((float)y[t].x, (float)y[t].y);
+    }
+    if (lane == 0) *info = 0;
+}
+
 // Cholesky solve of (A + delta I) h = b in FP64 by one wave, delta = ridge *
 // mean(Re diag A).  Lane l owns rows l, l + 64, ... (R slots).  The factor is
 // stored by columns, F[k ld + r] = L[r][k] (ld = 64 in LDS, where K <= 64,
@@ -607,71 +683,92 @@ __global__ void __launch_bounds__(64) ls_solve_kernel(const double2 *__restrict_
         __syncthreads();
     }
 
-    // L y = b, then L^H h = y, both on the rows' registers
-    double invd[R];   // 1 / L[r][r] of the owned rows
-#pragma unroll
-    for (int t = 0; t < R; ++t) invd[t] = 1.0 / F[rc[t] * ld + rc[t]].x;
-    double2 y[R], f[R];
-#pragma unroll
-    for (int t = 0; t < R; ++t) {
-        const int r = lane + 64 * t;
-        y[t] = r < K ? b[r] : make_double2(0.0, 0.0);
-        f[t] = F[rc[t]];   // column 0
+    ls_substitute<R>(F, ld, b, K, h, info, lane);
+}
+
+// The same solve for K <= kLsSolve4MaxK on four waves: F in LDS (column
+// stride 64); the sums of column j are split over the waves (lane = row r,
+// wave w the columns k = w, w + 4, ... < j, two partial sums each) and added
+// up in LDS in wave order; wave 0 takes the pivot from its owner lane, stores
+// the column and, at the end, runs the substitutions.  One barrier after the
+// partial sums and one after the column.
+constexpr int kLsSolve4MaxK = 56;   // F and the partial sums within 64 KiB of LDS
+__global__ void __launch_bounds__(256) ls_solve4_kernel(const double2 *__restrict__ A,
+                                                        const double2 *__restrict__ b, int K, double ridge,
+                                                        float2 *__restrict__ h, int32_t *__restrict__ info)
+{
+    extern __shared__ double2 ls_smem[];
+    double2 *F = ls_smem;             // K columns of 64
+    double2 *part = ls_smem + 64 * K; // 4 x 64 partial sums
+    __shared__ int failed;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int rc = min(lane, K - 1);
+    // F = strict lower triangle of A, zero elsewhere (the diagonal included)
+    for (int e = tid; e < 64 * K; e += 256) {
+        const int k = e >> 6, r = e & 63;
+        F[e] = (r < K && r > k) ? A[(int64_t)r * K + k] : make_double2(0.0, 0.0);
     }
+    double dg = 0.0;   // Re A[r][r] + delta of the lane's row (wave 0)
+    if (w == 0) {
+        double tr = 0.0;
+        for (int i = lane; i < K; i += 64) tr += A[(int64_t)i * K + i].x;
+        const double delta = ridge * ls_wave_sum(tr) / K;
+        dg = A[(int64_t)rc * K + rc].x + delta;
+        if (lane == 0) failed = 0;
+    }
+    __syncthreads();
     for (int j = 0; j < K; ++j) {
-        double2 fn[R];
-        const int jn = min(j + 1, K - 1);
-#pragma unroll
-        for (int t = 0; t < R; ++t) fn[t] = F[jn * ld + rc[t]];   // L[r][j+1]
-        double2 mine = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int t = 0; t < R; ++t)
-            if (t == (j >> 6)) mine = make_double2(y[t].x * invd[t], y[t].y * invd[t]);
-        const double2 yj = make_double2(ls_bcast(mine.x, j & 63), ls_bcast(mine.y, j & 63));
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            const int r = lane + 64 * t;
-            if (r == j) {
-                y[t] = yj;
-            } else if (r > j) {
-                // y_r -= L[r][j] y_j
-                y[t].x -= f[t].x * yj.x - f[t].y * yj.y;
-                y[t].y -= f[t].x * yj.y + f[t].y * yj.x;
-            }
-            f[t] = fn[t];
+        // -sum_{k = w mod 4, k < j} L[r][k] conj(L[j][k])
+        double2 s0 = make_double2(0.0, 0.0), s1 = s0;
+        int k = w;
+        for (; k + 4 < j; k += 8) {
+            const double2 c0 = F[k * 64 + j], a0 = F[k * 64 + rc];
+            const double2 c1 = F[(k + 4) * 64 + j], a1 = F[(k + 4) * 64 + rc];
+            s0.x = fma(-a0.x, c0.x, s0.x);
+            s0.x = fma(-a0.y, c0.y, s0.x);
+            s0.y = fma(-a0.y, c0.x, s0.y);
+            s0.y = fma(a0.x, c0.y, s0.y);
+            s1.x = fma(-a1.x, c1.x, s1.x);
+            s1.x = fma(-a1.y, c1.y, s1.x);
+            s1.y = fma(-a1.y, c1.x, s1.y);
+            s1.y = fma(a1.x, c1.y, s1.y);
         }
-    }
-#pragma unroll
-    for (int t = 0; t < R; ++t) f[t] = F[rc[t] * ld + (K - 1)];   // L[K-1][r]
-    for (int j = K - 1; j >= 0; --j) {
-        double2 fn[R];
-        const int jn = max(j - 1, 0);
-#pragma unroll
-        for (int t = 0; t < R; ++t) fn[t] = F[rc[t] * ld + jn];   // L[j-1][r]
-        double2 mine = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int t = 0; t < R; ++t)
-            if (t == (j >> 6)) mine = make_double2(y[t].x * invd[t], y[t].y * invd[t]);
-        const double2 hj = make_double2(ls_bcast(mine.x, j & 63), ls_bcast(mine.y, j & 63));
-#pragma unroll
-        for (int t = 0; t < R; ++t) {
-            const int r = lane + 64 * t;
-            if (r == j) {
-                y[t] = hj;
-            } else if (r < j) {
-                // y_r -= conj(L[j][r]) h_j
-                y[t].x -= f[t].x * hj.x + f[t].y * hj.y;
-                y[t].y -= f[t].x * hj.y - f[t].y * hj.x;
-            }
-            f[t] = fn[t];
+        if (k < j) {
+            const double2 c0 = F[k * 64 + j], a0 = F[k * 64 + rc];
+            s0.x = fma(-a0.x, c0.x, s0.x);
+            s0.x = fma(-a0.y, c0.y, s0.x);
+            s0.y = fma(-a0.y, c0.x, s0.y);
+            s0.y = fma(a0.x, c0.y, s0.y);
         }
-    }
+        part[w * 64 + lane] = make_double2(s0.x + s1.x, s0.y + s1.y);
+        __syncthreads();
+        if (w == 0) {
+            double2 s = F[j * 64 + rc];
+            if (lane == j) s.x += dg;
 #pragma unroll
-    for (int t = 0; t < R; ++t) {
-        const int r = lane + 64 * t;
-        if (r < K) h[r] = make_float2((float)y[t].x, (float)y[t].y);
+            for (int q = 0; q < 4; ++q) {
+                s.x += part[q * 64 + lane].x;
+                s.y += part[q * 64 + lane].y;
+            }
+            const double piv = ls_bcast(s.x, j);
+            if (!(piv > 0.0)) {
+                for (int i = lane; i < K; i += 64) h[i] = make_float2(NAN, NAN);
+                if (lane == 0) {
+                    *info = j + 1;
+                    failed = 1;
+                }
+            } else {
+                const double d = sqrt(piv), inv = 1.0 / d;
+                if (lane == j)
+                    F[j * 64 + lane] = make_double2(d, 0.0);
+                else if (lane > j && lane < K)
+                    F[j * 64 + lane] = make_double2(s.x * inv, s.y * inv);
+            }
+        }
+        __syncthreads();
+        if (failed) return;
     }
-    if (lane == 0) *info = 0;
+    if (w == 0) ls_substitute<1>(F, 64, b, K, h, info, lane);
 }
 
 __global__ void __launch_bounds__(kBlock) ls_zero_kernel(double2 *__restrict__ p, int64_t count)
@@ -948,7 +1045,10 @@ DPD_EXPORT dpd_status dpd_ls_solve(void *stream, int32_t K, const void *A, const
     double2 *F = (double2 *)ws;
     float2 *hd = (float2 *)h;
     int32_t *id = (int32_t *)info;
-    if (in_lds)
+    if (K <= kLsSolve4MaxK)
+        hipLaunchKernelGGL(ls_solve4_kernel, dim3(1), dim3(256), (size_t)(64 * K + 4 * 64) * sizeof(double2), st,
+                           Ad, bd, K, ridge, hd, id);
+    else if (in_lds)
         hipLaunchKernelGGL((ls_solve_kernel<true, 1>), dim3(1), dim3(64), lds, st, Ad, bd, K, ridge, F, hd, id);
     else if (R == 2)
         hipLaunchKernelGGL((ls_solve_kernel<false, 2>), dim3(1), dim3(64), 0, st, Ad, bd, K, ridge, F, hd, id);

@@ -150,11 +150,11 @@ def test_solve_matches_numpy(torch, dpd, orc, mo, co, L):
         assert rel <= 1e-6, (ridge, rel)
 
 
-@pytest.mark.parametrize("K", [1, 2, 63, 64, 65, 130, 300])
+@pytest.mark.parametrize("K", [1, 2, 33, 56, 57, 63, 64, 65, 130, 300])
 def test_solve_random_sizes(torch, dpd, K):
-    """Every row layout of the one-wave solve (1, 2, 4 and 8 rows per lane; the
-    factor in LDS up to K = 64) against numpy on a random Hermitian positive
-    definite matrix."""
+    """Every solve kernel against numpy on a random Hermitian positive definite
+    matrix: four waves up to K = 56, then one wave with the factor in LDS up to
+    K = 64 and 2, 4 and 8 rows per lane beyond."""
     rng = np.random.default_rng(K)
     X = rng.standard_normal((2 * K + 8, K)) + 1j * rng.standard_normal((2 * K + 8, K))
     A = X.conj().T @ X
@@ -178,6 +178,13 @@ def test_solve_reports_indefinite(torch, dpd):
     A2[2, 2] = 0
     _, info2 = dpd.ls_solve(A2, b)
     assert int(info2.item()) == 3
+    # the same through the one-wave kernel (K above the four-wave limit)
+    K = 60
+    A3 = torch.eye(K, dtype=torch.complex128, device="cuda")
+    A3[41, 41] = -1
+    h3, info3 = dpd.ls_solve(A3, torch.ones(K, dtype=torch.complex128, device="cuda"))
+    assert int(info3.item()) == 42
+    assert torch.isnan(h3.real).all()
 
 
 def test_recovers_generating_coefficients(torch, dpd, orc):
