@@ -284,7 +284,7 @@ dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y, const void
  *   info: device int32, set to 0 on success or j+1 when the pivot of column j
  *   is not positive (h is then NaN); the host sees it after synchronizing.
  *   ws: device, >= dpd_ls_solve_ws_size bytes (K*K complex128), 16-byte
- *   aligned (used for K > 56; smaller systems are factored in shared
+ *   aligned (used for K > 64; smaller systems are factored in shared
  *   memory).  One workgroup (four wavefronts up to K = 56, one beyond);
  *   DPD_EUNSUPPORTED for K > 1024. */
 dpd_status dpd_ls_solve_ws_size(int32_t K, size_t *bytes);
