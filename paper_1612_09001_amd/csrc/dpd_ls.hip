@@ -418,12 +418,18 @@ __global__ void __launch_bounds__(kBlock) ls_reduce1_kernel(const float *__restr
 }
 
 // Second level: sum the groups in order and scatter the tile element into the
-// full symmetric R (Dp x Dp, FP64).
+// full symmetric R (Dp x Dp, FP64).  In a diagonal tile only the elements on
+// and above its diagonal are used (each writes itself and its mirror), so R
+// is symmetric by construction.
 __global__ void __launch_bounds__(kBlock) ls_reduce2_kernel(const double *__restrict__ r1, int64_t groups, int64_t E,
                                                             int nt, int Dp, double *__restrict__ R)
 {
     const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (e >= E) return;
+    int I, J;
+    ls_pair((int)(e / 256), nt, I, J);
+    const int ri = (int)((e % 256) / 16), ci = (int)(e % 16);
+    if (I == J && ri > ci) return;
     double t = 0.0;
     int64_t g = 0;
     for (; g + 8 <= groups; g += 8) {
@@ -434,9 +440,7 @@ __global__ void __launch_bounds__(kBlock) ls_reduce2_kernel(const double *__rest
         for (int i = 0; i < 8; ++i) t += v[i];
     }
     for (; g < groups; ++g) t += r1[g * E + e];
-    int I, J;
-    ls_pair((int)(e / 256), nt, I, J);
-    const int i = 16 * I + (int)((e % 256) / 16), j = 16 * J + (int)(e % 16);
+    const int i = 16 * I + ri, j = 16 * J + ci;
     R[(int64_t)i * Dp + j] = t;
     R[(int64_t)j * Dp + i] = t;
 }
