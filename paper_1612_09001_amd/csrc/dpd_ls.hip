@@ -73,17 +73,6 @@ struct LsParams {
     int8_t slot[kLsRoles];  // LDS row slot of each basis entry
 };
 
-// Tile pair q of the upper triangle, row-major over (I <= J).
-__device__ __forceinline__ void ls_pair(int q, int nt, int &I, int &J)
-{
-    I = 0;
-    while (q >= nt - I) {
-        q -= nt - I;
-        ++I;
-    }
-    J = I + q;
-}
-
 // Tile pair q of the upper triangle, row-major over (I <= J), at compile time.
 constexpr int ls_pair_i(int q, int nt)
 {
@@ -417,53 +406,6 @@ __global__ void __launch_bounds__(kBlock) ls_reduce1_kernel(const float *__restr
     r1[g * E + e] = t;
 }
 
-// Second level: sum the groups in order and scatter the tile element into the
-// full symmetric R (Dp x Dp, FP64).  In a diagonal tile only the elements on
-// and above its diagonal are used (each writes itself and its mirror), so R
-// is symmetric by construction.
-__global__ void __launch_bounds__(kBlock) ls_reduce2_kernel(const double *__restrict__ r1, int64_t groups, int64_t E,
-                                                            int nt, int Dp, double *__restrict__ R)
-{
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= E) return;
-    int I, J;
-    ls_pair((int)(e / 256), nt, I, J);
-    const int ri = (int)((e % 256) / 16), ci = (int)(e % 16);
-    if (I == J && ri > ci) return;
-    double t = 0.0;
-    int64_t g = 0;
-    for (; g + 8 <= groups; g += 8) {
-        double v[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = r1[(g + i) * E + e];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) t += v[i];
-    }
-    for (; g < groups; ++g) t += r1[g * E + e];
-    const int i = 16 * I + ri, j = 16 * J + ci;
-    R[(int64_t)i * Dp + j] = t;
-    R[(int64_t)j * Dp + i] = t;
-}
-
-// A (K x K) and b (K) from R.
-__global__ void __launch_bounds__(kBlock) ls_assemble_kernel(const double *__restrict__ R, int K, int Dp,
-                                                             double2 *__restrict__ A, double2 *__restrict__ b)
-{
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e < (int64_t)K * K) {
-        const int a = (int)(e / K), c = (int)(e % K);
-        const double re = R[(int64_t)a * Dp + c] + R[(int64_t)(K + a) * Dp + K + c];
-        const double im = R[(int64_t)a * Dp + K + c] - R[(int64_t)(K + a) * Dp + c];
-        A[e] = make_double2(re, im);
-    } else if (e < (int64_t)K * K + K) {
-        const int a = (int)(e - (int64_t)K * K);
-        const int tr = 2 * K, ti = 2 * K + 1;
-        const double re = R[(int64_t)a * Dp + tr] + R[(int64_t)(K + a) * Dp + ti];
-        const double im = R[(int64_t)a * Dp + ti] - R[(int64_t)(K + a) * Dp + tr];
-        b[a] = make_double2(re, im);
-    }
-}
-
 // Sum over the 64 lanes of a wave in FP64 (fixed butterfly: every lane gets
 // the same total).
 __device__ __forceinline__ double ls_wave_sum(double v)
@@ -480,6 +422,60 @@ __device__ __forceinline__ double ls_bcast(double v, int src)
     const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffll), src);
     const int hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Index of the real-Gram entry R[i][j] (either order) in a slab's tile list:
+// the upper-triangle element, so R is symmetric by construction.
+__device__ __forceinline__ int64_t ls_entry(int i, int j, int nt)
+{
+    if (i > j) {
+        const int t = i;
+        i = j;
+        j = t;
+    }
+    const int I = i >> 4, J = j >> 4;
+    const int q = I * nt - I * (I - 1) / 2 + (J - I);   // row-major upper-triangle pair
+    return (int64_t)q * 256 + (i & 15) * 16 + (j & 15);
+}
+
+// Second level and assembly: one wave per output (A row-major, then b).  Lane
+// g sums groups g, g + 64, ... of the four real-Gram entries the output needs
+// (in group order), a fixed butterfly adds the lanes, and
+//   A[a][c] = (R[a][c] + R[K+a][K+c]) + i (R[a][K+c] - R[K+a][c]),
+//   b[a]    = (R[a][tr] + R[K+a][ti]) + i (R[a][ti] - R[K+a][tr]),
+// tr, ti = 2K, 2K+1.  A[c][a] reads the same entries, so A is Hermitian.
+__global__ void __launch_bounds__(kBlock) ls_finish_kernel(const double *__restrict__ r1, int64_t groups, int64_t E,
+                                                           int nt, int K, double2 *__restrict__ A,
+                                                           double2 *__restrict__ b)
+{
+    const int64_t o = (int64_t)blockIdx.x * kLsWaves + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (o >= (int64_t)K * K + K) return;   // the whole wave
+    int a, c0, c1;                         // rows a, K + a against columns c0, c1
+    if (o < (int64_t)K * K) {
+        a = (int)(o / K);
+        c0 = (int)(o % K);
+        c1 = K + c0;
+    } else {
+        a = (int)(o - (int64_t)K * K);
+        c0 = 2 * K;
+        c1 = 2 * K + 1;
+    }
+    const int64_t e[4] = {ls_entry(a, c0, nt), ls_entry(K + a, c1, nt), ls_entry(a, c1, nt),
+                          ls_entry(K + a, c0, nt)};
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t g = lane; g < groups; g += 64)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] += r1[g * E + e[t]];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = ls_wave_sum(v[t]);
+    if (lane == 0) {
+        const double2 r = make_double2(v[0] + v[1], v[2] - v[3]);
+        if (o < (int64_t)K * K)
+            A[o] = r;
+        else
+            b[a] = r;
+    }
 }
 
 // L y = b, then L^H h = y on the factor F (column-major at stride ld, the
@@ -811,7 +807,7 @@ static LsShape ls_shape(const CoefMap &map)
 }
 
 struct LsWs {
-    size_t partials, r1, R, total;
+    size_t partials, r1, total;
 };
 
 // Samples per block: 4096 on large inputs; smaller (down to 1024) when that
@@ -836,8 +832,7 @@ static LsWs ls_ws(const LsShape &s, int64_t rows, int64_t n)
     LsWs w;
     w.partials = up((size_t)(nslabs * E) * sizeof(float));
     w.r1 = up((size_t)(groups * E) * sizeof(double));
-    w.R = up((size_t)s.Dp * s.Dp * sizeof(double));
-    w.total = w.partials + w.r1 + w.R;
+    w.total = w.partials + w.r1;
     return w;
 }
 
@@ -963,7 +958,6 @@ DPD_EXPORT dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y,
     char *base = (char *)ws;
     float *partials = (float *)base;
     double *r1 = (double *)(base + w.partials);
-    double *R = (double *)(base + w.partials + w.r1);
     const int64_t slab = ls_slab(rows, n);
     const int64_t spr = (n + slab - 1) / slab;
     const int64_t nslabs = rows * spr;
@@ -1009,14 +1003,9 @@ DPD_EXPORT dpd_status dpd_ls_normal(dpd_plan *plan, void *stream, const void *y,
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(ls_reduce2_kernel, dim3(eb), dim3(kBlock), 0, st, (const double *)r1, groups, E, s.nt,
-                           s.Dp, R);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
         const int64_t outs = (int64_t)s.K * s.K + s.K;
-        hipLaunchKernelGGL(ls_assemble_kernel, dim3((uint32_t)((outs + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
-                           (const double *)R, s.K, s.Dp, (double2 *)A, (double2 *)b);
+        hipLaunchKernelGGL(ls_finish_kernel, dim3((uint32_t)((outs + kLsWaves - 1) / kLsWaves)), dim3(kBlock), 0, st,
+                           (const double *)r1, groups, E, s.nt, s.K, (double2 *)A, (double2 *)b);
         e = hipGetLastError();
     }
     return e == hipSuccess ? DPD_OK : hip_fail(e);
