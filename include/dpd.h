@@ -265,7 +265,7 @@ dpd_status dpd_cascade_backward(const dpd_plan *A, const dpd_plan *B, void *stre
  *   caller-owned scratch.  A, b: device, 8-byte aligned, overwritten.  FP32
  *   features, each split into a bf16 high and low part for the matrix cores
  *   (all four cross products summed in FP32: FP32-level accuracy),
- *   accumulated in FP32 over slabs of 1024 to 4096 samples (the size
+ *   accumulated in FP32 over slabs of 1024 to 8192 samples (the size
  *   depends only on rows, n and the device's CU count), the slabs summed in
  *   FP64 in a fixed order: deterministic.  Allocates nothing, does not
  *   synchronize; rows * n == 0 gives A = 0, b = 0.  The first call on a plan

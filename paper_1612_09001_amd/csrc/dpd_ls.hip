@@ -19,9 +19,9 @@
 // bf16 rounding of its remainder, and the tap columns read it shifted; the four cross products of
 // every pair of features are summed in FP32 (the dropped terms are ~2^-17 of
 // each product, below FP32 accumulation error).  Each block covers one slab
-// of 1024..4096 samples (the size depends only on the input shape and the
+// of 1024..8192 samples (the size depends only on the input shape and the
 // number of CUs) and writes its FP32 tiles (each of the four waves adds at
-// most 128 eight-sample steps per accumulator; the four partial tiles are
+// most 256 eight-sample steps per accumulator; the four partial tiles are
 // summed in FP32); the slabs are summed in FP64 in a fixed order (two
 // levels), so the result is deterministic.
 #include <hip/hip_runtime.h>
@@ -45,7 +45,7 @@ typedef unsigned u32x4_ls __attribute__((ext_vector_type(4)));
 
 constexpr int kLsTile = 64;         // samples staged per step
 constexpr int kLsSolveMaxK = 1024;  // one wave, at most 16 rows per lane
-constexpr int kLsSlabMax = 4096;    // samples per block / FP32 partial (at most)
+constexpr int kLsSlabMax = 8192;    // samples per block / FP32 partial (at most)
 constexpr int kLsSlabMin = 1024;
 constexpr int kLsMaxDp = 192;       // padded real features (2K+2 rounded up to 16): K <= 95
 constexpr int kLsMaxNt = kLsMaxDp / 16;
@@ -810,7 +810,7 @@ struct LsWs {
     size_t partials, r1, total;
 };
 
-// Samples per block: 4096 on large inputs; smaller (down to 1024) when that
+// Samples per block: 8192 on large inputs; smaller (down to 1024) when that
 // leaves fewer than ~6 blocks per CU, so small fits still fill the chip.
 int num_cus();
 static int64_t ls_slab(int64_t rows, int64_t n)
