@@ -91,6 +91,20 @@ def test_normal_equations_match_oracle(torch, dpd, orc, mo, co, L, n):
     assert np.array_equal(An, An.conj().T)
 
 
+def test_normal_equations_full_size(torch, dpd, orc):
+    """The headline basis (K = 33) over the benchmark's 2^24 samples plus a
+    ragged tail of 777 (8192-sample slabs, the last one and its last tile
+    short), every entry of A and b against the FP64 oracle."""
+    mo = co = [1, 3, 5, 7]
+    L, n = 4, (1 << 24) + 777
+    y, t = _target(n, mo, co, L, seed=24)
+    plan = dpd.Plan(mo, co, L, signals.aph_coeffs(mo, co, L, config_id=3))
+    A, b = plan.ls_normal(_dev(torch, y), _dev(torch, t))
+    Ar, br = orc.ls_normal(y, mo, co, L, t)
+    ea, eb = _scaled_rel(A.cpu().numpy(), b.cpu().numpy(), Ar, br)
+    assert ea <= LS_REL_MAX and eb <= LS_REL_MAX, (ea, eb)
+
+
 def test_rows_scale_and_stride(torch, dpd, orc):
     mo, co, L, rows, n, ld = [1, 3, 5], [1, 3], 4, 3, 5000, 5008
     scale = 0.1
