@@ -689,9 +689,11 @@ __global__ void __launch_bounds__(64) ls_solve_kernel(const double2 *__restrict_
 // The same solve for K <= kLsSolve4MaxK on four waves: F in LDS (column
 // stride 64); the sums of column j are split over the waves (lane = row r,
 // wave w the columns k = w, w + 4, ... < j, two partial sums each) and added
-// up in LDS in wave order; wave 0 takes the pivot from its owner lane, stores
-// the column and, at the end, runs the substitutions.  One barrier after the
-// partial sums and one after the column.
+// up in wave order by every wave after one barrier, so all waves hold the
+// same column; wave j mod 4 stores it, and only that wave reads it later (it
+// owns k = j), so the column needs no second barrier.  The partial sums
+// alternate between two LDS buffers; each lane reads its A entry of column j
+// before the barrier.  Wave 0 runs the substitutions at the end.
 constexpr int kLsSolve4MaxK = 56;   // F and the partial sums within 64 KiB of LDS
 __global__ void __launch_bounds__(256) ls_solve4_kernel(const double2 *__restrict__ A,
                                                         const double2 *__restrict__ b, int K, double ridge,
@@ -699,8 +701,7 @@ __global__ void __launch_bounds__(256) ls_solve4_kernel(const double2 *__restric
 {
     extern __shared__ double2 ls_smem[];
     double2 *F = ls_smem;             // K columns of 64
-    double2 *part = ls_smem + 64 * K; // 4 x 64 partial sums
-    __shared__ int failed;
+    double2 *part = ls_smem + 64 * K; // 2 x 4 x 64 partial sums
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int rc = min(lane, K - 1);
     // F = strict lower triangle of A, zero elsewhere (the diagonal included)
@@ -708,16 +709,13 @@ __global__ void __launch_bounds__(256) ls_solve4_kernel(const double2 *__restric
         const int k = e >> 6, r = e & 63;
         F[e] = (r < K && r > k) ? A[(int64_t)r * K + k] : make_double2(0.0, 0.0);
     }
-    double dg = 0.0;   // Re A[r][r] + delta of the lane's row (wave 0)
-    if (w == 0) {
-        double tr = 0.0;
-        for (int i = lane; i < K; i += 64) tr += A[(int64_t)i * K + i].x;
-        const double delta = ridge * ls_wave_sum(tr) / K;
-        dg = A[(int64_t)rc * K + rc].x + delta;
-        if (lane == 0) failed = 0;
-    }
+    double tr = 0.0;
+    for (int i = lane; i < K; i += 64) tr += A[(int64_t)i * K + i].x;
+    const double delta = ridge * ls_wave_sum(tr) / K;
+    const double dg = A[(int64_t)rc * K + rc].x + delta;   // Re A[r][r] + delta of the lane's row
     __syncthreads();
     for (int j = 0; j < K; ++j) {
+        const double2 aj = F[j * 64 + rc];   // A[r][j] (column j is not written before the barrier)
         // -sum_{k = w mod 4, k < j} L[r][k] conj(L[j][k])
         double2 s0 = make_double2(0.0, 0.0), s1 = s0;
         int k = w;
@@ -740,34 +738,33 @@ __global__ void __launch_bounds__(256) ls_solve4_kernel(const double2 *__restric
             s0.y = fma(-a0.y, c0.x, s0.y);
             s0.y = fma(a0.x, c0.y, s0.y);
         }
-        part[w * 64 + lane] = make_double2(s0.x + s1.x, s0.y + s1.y);
+        double2 *pj = part + (j & 1) * 256;
+        pj[w * 64 + lane] = make_double2(s0.x + s1.x, s0.y + s1.y);
         __syncthreads();
-        if (w == 0) {
-            double2 s = F[j * 64 + rc];
-            if (lane == j) s.x += dg;
+        double2 s = aj;
+        if (lane == j) s.x += dg;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                s.x += part[q * 64 + lane].x;
-                s.y += part[q * 64 + lane].y;
-            }
-            const double piv = ls_bcast(s.x, j);
-            if (!(piv > 0.0)) {
-                for (int i = lane; i < K; i += 64) h[i] = make_float2(NAN, NAN);
-                if (lane == 0) {
-                    *info = j + 1;
-                    failed = 1;
-                }
-            } else {
-                const double d = sqrt(piv), inv = 1.0 / d;
-                if (lane == j)
-                    F[j * 64 + lane] = make_double2(d, 0.0);
-                else if (lane > j && lane < K)
-                    F[j * 64 + lane] = make_double2(s.x * inv, s.y * inv);
-            }
+        for (int q = 0; q < 4; ++q) {
+            s.x += pj[q * 64 + lane].x;
+            s.y += pj[q * 64 + lane].y;
         }
-        __syncthreads();
-        if (failed) return;
+        const double piv = ls_bcast(s.x, j);
+        if (!(piv > 0.0)) {   // the same in every wave
+            if (w == 0) {
+                for (int i = lane; i < K; i += 64) h[i] = make_float2(NAN, NAN);
+                if (lane == 0) *info = j + 1;
+            }
+            return;
+        }
+        if (w == (j & 3)) {
+            const double d = sqrt(piv), inv = 1.0 / d;
+            if (lane == j)
+                F[j * 64 + lane] = make_double2(d, 0.0);
+            else if (lane > j && lane < K)
+                F[j * 64 + lane] = make_double2(s.x * inv, s.y * inv);
+        }
     }
+    __syncthreads();   // every column stored
     if (w == 0) ls_substitute<1>(F, 64, b, K, h, info, lane);
 }
 
@@ -1039,7 +1036,7 @@ DPD_EXPORT dpd_status dpd_ls_solve(void *stream, int32_t K, const void *A, const
     float2 *hd = (float2 *)h;
     int32_t *id = (int32_t *)info;
     if (K <= kLsSolve4MaxK)
-        hipLaunchKernelGGL(ls_solve4_kernel, dim3(1), dim3(256), (size_t)(64 * K + 4 * 64) * sizeof(double2), st,
+        hipLaunchKernelGGL(ls_solve4_kernel, dim3(1), dim3(256), (size_t)(64 * K + 2 * 4 * 64) * sizeof(double2), st,
                            Ad, bd, K, ridge, hd, id);
     else if (in_lds)
         hipLaunchKernelGGL((ls_solve_kernel<true, 1>), dim3(1), dim3(64), lds, st, Ad, bd, K, ridge, F, hd, id);
