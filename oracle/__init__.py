@@ -9,3 +9,4 @@ from .oracle import (  # noqa: F401
 )
 from . import brute  # noqa: F401
 from . import pa  # noqa: F401,E402
+from . import ila  # noqa: F401,E402

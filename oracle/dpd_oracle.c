@@ -317,6 +317,26 @@ int oracle_backward(const double *x, int64_t n, const double *hist,
  * are dropped, matching an output of M samples), and t is the target sequence.
  * A is row-major, 2*K*K doubles; b is 2*K doubles.
  */
+/* Row m of Psi (K complex entries, section 2.2 stacking) into row[]. */
+static void ls_row(const double *y, int64_t m, const int32_t *mo, int32_t nm, const int32_t *co,
+                   int32_t nc, int32_t L, double *row)
+{
+    int64_t col = 0;
+    for (int32_t br = 0; br < nm + nc; ++br) {
+        int is_conj = br >= nm;
+        int32_t p = is_conj ? co[br - nm] : mo[br];
+        for (int32_t k = 0; k < L; ++k, ++col) {
+            double xr, xi, pr, pi;
+            sample_at(y, NULL, L, m - k, &xr, &xi);
+            psi(p, xr, xi, &pr, &pi);
+            row[2 * col] = pr;
+            row[2 * col + 1] = is_conj ? -pi : pi;
+        }
+    }
+    row[2 * col] = 1.0;
+    row[2 * col + 1] = 0.0;
+}
+
 int oracle_ls_normal(const double *y, int64_t M, const int32_t *main_orders, int32_t n_main,
                      const int32_t *conj_orders, int32_t n_conj, int32_t L,
                      const double *t, double *A, double *b)
@@ -325,33 +345,35 @@ int oracle_ls_normal(const double *y, int64_t M, const int32_t *main_orders, int
         return ORACLE_EINVAL;
     if (!A || !b || (M > 0 && (!y || !t))) return ORACLE_EINVAL;
     const int64_t K = (int64_t)(n_main + n_conj) * L + 1;
-    double *row = (double *)malloc(sizeof(double) * 2 * (size_t)K);
-    if (!row) return ORACLE_EINVAL;
     memset(A, 0, sizeof(double) * 2 * (size_t)(K * K));
     memset(b, 0, sizeof(double) * 2 * (size_t)K);
-    for (int64_t m = 0; m < M; ++m) {
-        int64_t col = 0;
-        for (int32_t br = 0; br < n_main + n_conj; ++br) {
-            int is_conj = br >= n_main;
-            int32_t p = is_conj ? conj_orders[br - n_main] : main_orders[br];
-            for (int32_t k = 0; k < L; ++k, ++col) {
-                double xr, xi, pr, pi;
-                sample_at(y, NULL, L, m - k, &xr, &xi);
-                psi(p, xr, xi, &pr, &pi);
-                row[2 * col] = pr;
-                row[2 * col + 1] = is_conj ? -pi : pi;
+    int failed = 0;
+    /* Threads take bands of rows i of A (and entries of b); every entry is one
+       sum over m in increasing order, so the result does not depend on the
+       thread count. */
+#pragma omp parallel
+    {
+        double *row = (double *)malloc(sizeof(double) * 2 * (size_t)K);
+        if (!row) {
+#pragma omp atomic write
+            failed = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t i0 = 0; i0 < K; i0 += 4) {
+            if (!row) continue;
+            const int64_t i1 = i0 + 4 < K ? i0 + 4 : K;
+            for (int64_t m = 0; m < M; ++m) {
+                ls_row(y, m, main_orders, n_main, conj_orders, n_conj, L, row);
+                for (int64_t i = i0; i < i1; ++i) {
+                    /* conj(row_i) * row_j and conj(row_i) * t_m */
+                    double ir = row[2 * i], ii = -row[2 * i + 1];
+                    for (int64_t j = 0; j < K; ++j)
+                        cmac(&A[2 * (i * K + j)], &A[2 * (i * K + j) + 1], ir, ii, row[2 * j], row[2 * j + 1]);
+                    cmac(&b[2 * i], &b[2 * i + 1], ir, ii, t[2 * m], t[2 * m + 1]);
+                }
             }
         }
-        row[2 * col] = 1.0;
-        row[2 * col + 1] = 0.0;
-        for (int64_t i = 0; i < K; ++i) {
-            /* conj(row_i) * row_j and conj(row_i) * t_m */
-            double ir = row[2 * i], ii = -row[2 * i + 1];
-            for (int64_t j = 0; j < K; ++j)
-                cmac(&A[2 * (i * K + j)], &A[2 * (i * K + j) + 1], ir, ii, row[2 * j], row[2 * j + 1]);
-            cmac(&b[2 * i], &b[2 * i + 1], ir, ii, t[2 * m], t[2 * m + 1]);
-        }
+        free(row);
     }
-    free(row);
-    return ORACLE_OK;
+    return failed ? ORACLE_EINVAL : ORACLE_OK;
 }

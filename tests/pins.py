@@ -373,4 +373,167 @@ def pin_ls_normal(orc):
     assert _rel(hh, h) < 1e-8
 
 
+def pin_forward_at_matches_forward(orc):
+    """Evaluating Eq. (1) at listed output indices gives exactly the entries of
+    the whole-stream result at those indices (any order, repeats, the first and
+    the last output), with and without a carried history."""
+    g = _rng(14)
+    mo, co, L = [1, 3, 5, 7], [1, 3, 5], 5
+    n = 257
+    x = _cx(g, n, 0.6)
+    h = _coeffs(g, mo, co, L)
+    idx = np.concatenate([[n - 1, 0, 1, 3, 3], g.integers(0, n, 40)])
+    for hist in (None, _cx(g, L - 1, 0.6)):
+        z = orc.forward(x, mo, co, L, h, hist=hist)
+        za = orc.forward_at(x, mo, co, L, h, idx, hist=hist)
+        assert np.array_equal(za, z[idx])
+
+
+# ------------------------------------ transmitter chain (oracle/pa.py) ---
+# The learning workload's loss: predistorter -> I/Q imbalance + LO leakage ->
+# memory PA (Eq. 3 coefficients) -> E = mean |y/10 - x|^2.  The chain pins take
+# the module holding ``chain_loss_and_gradient`` so the mutation tests can hand
+# them planted copies of it.
+
+CHAIN_ORDERS = ([1, 3, 5], [1, 3])
+CHAIN_L = 3
+
+
+def _pa_module(pa_mod):
+    if pa_mod is None:
+        import oracle.pa as pa_mod
+    return pa_mod
+
+
+def _chain_inputs(seed):
+    """Two rows of 300 complex64 samples and coefficients away from any optimum."""
+    g = _rng(seed)
+    x = np.stack([_cx(g, 300, 0.3) for _ in range(2)]).astype(np.complex64)
+    h = _coeffs(g, *CHAIN_ORDERS, CHAIN_L)
+    h[0] += 1.0                       # near the identity, so the PA sees a sensible drive
+    return x, h
+
+
+def pin_chain_gradient_fd(orc, pa_mod=None):
+    """dE/dcoeffs of the chain equals FP64 central differences of E on Re and Im
+    of every coefficient (both rows summed)."""
+    pa = _pa_module(pa_mod)
+    x, h = _chain_inputs(400)
+    E, gc = pa.chain_loss_and_gradient(orc, x, CHAIN_ORDERS, CHAIN_L, h)
+    eps = 1e-6
+    fd = np.zeros(h.size, dtype=np.complex128)
+    for j in range(h.size):
+        for unit in (1.0, 1j):
+            hp = h.copy()
+            hm = h.copy()
+            hp[j] += unit * eps
+            hm[j] -= unit * eps
+            ep = pa.chain_loss_and_gradient(orc, x, CHAIN_ORDERS, CHAIN_L, hp)[0]
+            em = pa.chain_loss_and_gradient(orc, x, CHAIN_ORDERS, CHAIN_L, hm)[0]
+            fd[j] += (ep - em) / (2 * eps) * unit
+    assert _rel(gc, fd) < 1e-7, _rel(gc, fd)
+
+
+def pin_chain_loss_independent(orc, pa_mod=None):
+    """The chain loss equals E rebuilt from the definitions by another route: the
+    predistorter as Psi @ h of Eq. (2); the modulator as u = mu z + nu conj(z) +
+    c_LO with mu = (1 + g e^{-j phi})/2, nu = (1 - g e^{j phi})/2 (g = 1.05,
+    phi = 3 degrees, c_LO = 0.01 e^{j pi/4}); the PA as
+    10 sum_p alpha_p (beta * psi_p(u)) with the Eq. (3) coefficients of the
+    golden file and the memory taps beta = [1, -0.08+0.04j, 0.02-0.01j], by
+    numpy convolution.  Stage coefficients are rounded to complex64, as the
+    library receives them."""
+    pa = _pa_module(pa_mod)
+    x, h = _chain_inputs(401)
+    E, _ = pa.chain_loss_and_gradient(orc, x, CHAIN_ORDERS, CHAIN_L, h)
+    alpha = dict(load_eq3_alpha())
+    beta = np.array([1.0, -0.08 + 0.04j, 0.02 - 0.01j])
+    amp, phi = 1.05, np.deg2rad(3.0)
+    mu = complex(np.complex64((1 + amp * np.exp(-1j * phi)) / 2))
+    nu = complex(np.complex64((1 - amp * np.exp(1j * phi)) / 2))
+    lo = complex(np.complex64(0.01 * np.exp(1j * np.pi / 4)))
+    total = 0.0
+    for row in x:
+        z = brute.forward_matrix(row, *CHAIN_ORDERS, CHAIN_L, h)
+        u = mu * z + nu * np.conj(z) + lo
+        y = np.zeros_like(u)
+        for p in (1, 3, 5):
+            taps = (10.0 * alpha[p] * beta).astype(np.complex64).astype(np.complex128)
+            y += np.convolve(brute.basis(u, p), taps)[:u.size]
+        total += float(np.sum(np.abs(y / 10.0 - row.astype(np.complex128)) ** 2))
+    ref = total / x.size
+    assert abs(E - ref) <= 1e-11 * ref, (E, ref)
+
+
+# ------------------------------ indirect learning (oracle/ila.py) ---------
+
+def _ila_module(ila_mod):
+    if ila_mod is None:
+        import oracle.ila as ila_mod
+    return ila_mod
+
+
+def pin_ila_inverts_widely_linear_transmitter(orc, ila_mod=None):
+    """A transmitter u = mu z + nu conj(z) + c_LO followed by a complex gain G a
+    has an exact inverse in the basis (order 1 in both branches, c):
+    h_1 = conj(mu) / (a D), hbar_1 = -nu / (conj(a) D),
+    c = -(conj(mu) c_LO - nu conj(c_LO)) / D with D = |mu|^2 - |nu|^2, every
+    other coefficient 0.  One iteration from the identity must find it, and the
+    linearization error must then vanish."""
+    ila = _ila_module(ila_mod)
+    g = _rng(15)
+    mu, nu, lo = 0.97 + 0.05j, 0.03 - 0.02j, 0.02 - 0.01j
+    G, a = 10.0, 0.8 * np.exp(0.3j)
+    stages = [([1], [1], 1, np.array([mu, nu, lo])), ([1], [], 1, np.array([G * a, 0.0]))]
+    orders, L = ([1, 3, 5], [1, 3]), 2
+    x = np.stack([_cx(g, 400, 0.4) for _ in range(2)])
+    K = (len(orders[0]) + len(orders[1])) * L + 1
+    h0 = np.zeros(K, dtype=np.complex128)
+    h0[0] = 1.0
+    D = abs(mu) ** 2 - abs(nu) ** 2
+    ref = np.zeros(K, dtype=np.complex128)
+    ref[0] = np.conj(mu) / (a * D)
+    ref[len(orders[0]) * L] = -nu / (np.conj(a) * D)
+    ref[-1] = -(np.conj(mu) * lo - nu * np.conj(lo)) / D
+    errs, hs = ila.run(orc, x, orders, L, h0, 1, ridge=0.0, gain=G, stages=stages)
+    assert _rel(hs[0], ref) < 1e-9, _rel(hs[0], ref)
+    assert errs[1] < -200.0, errs
+
+
+def pin_ila_least_squares_route(orc, ila_mod=None):
+    """From coefficients away from the identity, one iteration on the synthetic
+    transmitter equals the ridge least-squares fit by another route: numpy's
+    lstsq of [Psi; sqrt(delta) I] h = [z; 0], with Psi the Eq. (2) basis matrix
+    of PA output / 10 (first M rows per row of input, stacked) and z the
+    predistorter output, delta = ridge * mean(Re diag Psi^H Psi)."""
+    import oracle.pa as opa
+
+    ila = _ila_module(ila_mod)
+    g = _rng(16)
+    orders, L = ([1, 3, 5], [1, 3]), 3
+    x = np.stack([_cx(g, 300, 0.25) for _ in range(2)]).astype(np.complex64)
+    h = 0.02 * _coeffs(g, *orders, L)
+    h[0] += 1.0
+    ridge = 1e-3
+    Ps, zs = [], []
+    for row in x:
+        z = brute.forward_matrix(row, *orders, L, h)
+        y = z
+        for smo, sco, sL, sh in opa.stages():
+            y = orc.forward(y, smo, sco, sL, sh)
+        Ps.append(brute.psi_matrix(y / 10.0, *orders, L)[:row.size])
+        zs.append(z)
+    P = np.concatenate(Ps)
+    t = np.concatenate(zs)
+    delta = ridge * float(np.mean(np.real(np.diag(P.conj().T @ P))))
+    K = P.shape[1]
+    Pa = np.concatenate([P, np.sqrt(delta) * np.eye(K)])
+    ta = np.concatenate([t, np.zeros(K)])
+    ref = np.linalg.lstsq(Pa, ta, rcond=None)[0]
+    hn = ila.iteration(orc, x, orders, L, h, ridge=ridge)
+    assert _rel(hn, ref) < 1e-8, _rel(hn, ref)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]
+CHAIN_PINS = [pin_chain_gradient_fd, pin_chain_loss_independent]
+ILA_PINS = [pin_ila_inverts_widely_linear_transmitter, pin_ila_least_squares_route]
