@@ -101,6 +101,14 @@ dpd_status dpd_set_coeffs(dpd_plan *plan, const float *coeffs_host);
  * Work on other streams that uses this plan must be ordered by the caller. */
 dpd_status dpd_set_coeffs_device(dpd_plan *plan, const void *coeffs_dev, void *stream);
 
+/* dpd_set_coeffs_device_if -- as dpd_set_coeffs_device, but only when the
+ * device int32 *flag_dev is 0 when the copy runs (stream order); otherwise
+ * the plan keeps its coefficients.  With the info output of dpd_ls_solve as
+ * the flag, a failed solve (NaN coefficients) never reaches the plan, without
+ * a host round trip.  flag_dev: device, 4-byte aligned, read only. */
+dpd_status dpd_set_coeffs_device_if(dpd_plan *plan, const void *coeffs_dev, const int32_t *flag_dev,
+                                    void *stream);
+
 /* dpd_set_tune / dpd_get_tune -- launch shape of this plan's forward kernels.
  * Fields outside the supported set are DPD_EINVAL. */
 dpd_status dpd_set_tune(dpd_plan *plan, const dpd_tune *tune);
@@ -123,7 +131,11 @@ dpd_status dpd_apply_rows(dpd_plan *plan, void *stream, const void *in, void *ou
 
 /* dpd_apply_coeffs -- as dpd_apply_rows, but the coefficients are read from a
  * device array of K complex64 (section 2.2 layout) in stream order, without a
- * host round trip (used by training).  The plan's own table is overwritten. */
+ * host round trip (used by training).  They are precombined into a second
+ * table of the plan, used only by calls that pass device coefficients (this
+ * one and dpd_backward with coeffs_dev): the plan's own coefficients stay as
+ * they were.  Such calls on one plan that overlap in time (different
+ * streams) race on that second table; order them, or use one plan each. */
 dpd_status dpd_apply_coeffs(dpd_plan *plan, void *stream, const void *coeffs_dev,
                             const void *in, void *out, int64_t rows, int64_t n, int64_t ld);
 
@@ -139,7 +151,9 @@ dpd_status dpd_apply_hist(dpd_plan *plan, void *stream, const void *in, void *ou
 /* --------------------------------------------------------------- backward --
  * Gradient of a real loss E through Eq. (1) (not in the paper).  Complex
  * gradients follow the convention dE/dRe + j dE/dIm (the one PyTorch uses).
- *   coeffs_dev   K complex64 on the device, or NULL to use the plan's
+ *   coeffs_dev   K complex64 on the device, or NULL to use the plan's (device
+ *                coefficients go through the plan's second table, as in
+ *                dpd_apply_coeffs; the plan's own coefficients are untouched)
  *   x            inputs of the forward call, rows x n with row stride ld
  *   grad_z       dE/dz for the outputs, same shape
  *   grad_x       receives dE/dx (same shape), or NULL to skip it

@@ -95,8 +95,10 @@ void precombine_host(const CoefMap &map, const float *raw, std::vector<float> &M
     M[4 * L * NI + 1] = raw[2 * (K - 1) + 1];
 }
 
-__global__ void prep_coeffs_kernel(const float2 *__restrict__ raw, CoefMap map, float *__restrict__ M)
+__global__ void prep_coeffs_kernel(const float2 *__restrict__ raw, CoefMap map, float *__restrict__ M,
+                                   const int32_t *__restrict__ flag)
 {
+    if (flag != nullptr && *flag != 0) return;   // conditional form: keep the table
     const int t = threadIdx.x;
     const int L = map.L, NI = map.NI;
     if (t < L * NI) {
@@ -117,10 +119,11 @@ __global__ void prep_coeffs_kernel(const float2 *__restrict__ raw, CoefMap map, 
     }
 }
 
-hipError_t launch_prep(const CoefMap &map, const void *raw, float *M, hipStream_t stream)
+hipError_t launch_prep(const CoefMap &map, const void *raw, float *M, hipStream_t stream,
+                       const int32_t *flag)
 {
     hipLaunchKernelGGL(prep_coeffs_kernel, dim3(1), dim3(kMaxL * kMaxNI), 0, stream,
-                       (const float2 *)raw, map, M);
+                       (const float2 *)raw, map, M, flag);
     return hipGetLastError();
 }
 
@@ -320,11 +323,12 @@ DPD_EXPORT dpd_status dpd_create(const int32_t *main_orders, int32_t n_main, con
         return hip_fail(e);
     }
     const size_t bytes = ((size_t)table_floats(L, map.NI) * sizeof(float) + 255) & ~(size_t)255;
-    e = hipMalloc((void **)&p->d_table, bytes);
+    e = hipMalloc((void **)&p->d_table, 2 * bytes);
     if (e != hipSuccess) {
         delete p;
         return e == hipErrorOutOfMemory ? DPD_ENOMEM : hip_fail(e);
     }
+    p->d_table_call = p->d_table + bytes / sizeof(float);
     std::vector<float> M;
     precombine_host(map, p->raw.data(), M);
     e = hipMemcpy(p->d_table, M.data(), M.size() * sizeof(float), hipMemcpyHostToDevice);
@@ -373,6 +377,15 @@ DPD_EXPORT dpd_status dpd_set_coeffs_device(dpd_plan *plan, const void *coeffs_d
     return e == hipSuccess ? DPD_OK : hip_fail(e);
 }
 
+DPD_EXPORT dpd_status dpd_set_coeffs_device_if(dpd_plan *plan, const void *coeffs_dev, const int32_t *flag_dev,
+                                               void *stream)
+{
+    if (plan == nullptr || coeffs_dev == nullptr || (uintptr_t)coeffs_dev % 8 != 0) return DPD_EINVAL;
+    if (flag_dev == nullptr || (uintptr_t)flag_dev % 4 != 0) return DPD_EINVAL;
+    hipError_t e = launch_prep(plan->map, coeffs_dev, plan->d_table, (hipStream_t)stream, flag_dev);
+    return e == hipSuccess ? DPD_OK : hip_fail(e);
+}
+
 DPD_EXPORT dpd_status dpd_set_tune(dpd_plan *plan, const dpd_tune *tune)
 {
     if (plan == nullptr || tune == nullptr || !valid_tune(*tune)) return DPD_EINVAL;
@@ -410,10 +423,10 @@ DPD_EXPORT dpd_status dpd_apply_coeffs(dpd_plan *plan, void *stream, const void 
     if (rows == 1 && ld < n) ld = n;
     dpd_status st = check_io(in, out, rows, n, ld);
     if (st != DPD_OK) return st;
-    hipError_t e = launch_prep(plan->map, coeffs_dev, plan->d_table, (hipStream_t)stream);
+    hipError_t e = launch_prep(plan->map, coeffs_dev, plan->d_table_call, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     if (n == 0 || rows == 0) return DPD_OK;
-    return run_forward(plan->map, plan->tune, plan->d_table, (hipStream_t)stream, in, out, rows, n,
+    return run_forward(plan->map, plan->tune, plan->d_table_call, (hipStream_t)stream, in, out, rows, n,
                        ld, nullptr);
 }
 

@@ -236,9 +236,11 @@ DPD_EXPORT dpd_status dpd_backward(dpd_plan *plan, void *stream, const void *coe
         };
         if (ov(grad_x, x) || ov(grad_x, grad_z)) return DPD_EINVAL;
     }
+    const float *table = plan->d_table;
     if (coeffs_dev != nullptr) {
-        hipError_t e = launch_prep(map, coeffs_dev, plan->d_table, st);
+        hipError_t e = launch_prep(map, coeffs_dev, plan->d_table_call, st);
         if (e != hipSuccess) return hip_fail(e);
+        table = plan->d_table_call;
     }
     if (!want_dx && !want_dc) return DPD_OK;
 
@@ -250,7 +252,7 @@ DPD_EXPORT dpd_status dpd_backward(dpd_plan *plan, void *stream, const void *coe
     p.n = n;
     p.ld = ld;
     p.rows = rows;
-    p.M = plan->d_table;
+    p.M = table;
     int nblk = 0;
     if (!empty) {
         const bool aligned = (uintptr_t)x % 16 == 0 && (uintptr_t)grad_z % 16 == 0 &&

@@ -20,10 +20,12 @@
 // every pair of features are summed in FP32 (the dropped terms are ~2^-17 of
 // each product, below FP32 accumulation error).  Each block covers one slab
 // of 1024..8192 samples (the size depends only on the input shape and the
-// number of CUs) and writes its FP32 tiles (each of the four waves adds at
-// most 256 eight-sample steps per accumulator; the four partial tiles are
-// summed in FP32); the slabs are summed in FP64 in a fixed order (two
-// levels), so the result is deterministic.
+// number of CUs) and writes its FP32 tiles (each FP32 accumulator adds the
+// eight-sample steps of a quarter of the slab -- at most 256 -- or, when the
+// basis needs 8 or more column tiles and the tile pairs split into two groups
+// of two waves, of half the slab -- at most 512; the partial tiles of the
+// waves are summed in FP32); the slabs are summed in FP64 in a fixed order
+// (two levels), so the result is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -763,6 +765,13 @@ __global__ void __launch_bounds__(256) ls_solve4_kernel(const double2 *__restric
             else if (lane > j && lane < K)
                 F[j * 64 + lane] = make_double2(s.x * inv, s.y * inv);
         }
+        // Column j is read again (by other lanes of the wave that stored it)
+        // before the next barrier: the LDS accesses of one wave execute in
+        // program order, and this keeps the compiler from moving those reads
+        // above the stores.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     __syncthreads();   // every column stored
     if (w == 0) ls_substitute<1>(F, 64, b, K, h, info, lane);

@@ -55,6 +55,7 @@ _SIGS = {
     "dpd_num_coeffs": [_vp, _i32p],
     "dpd_set_coeffs": [_vp, _f32p],
     "dpd_set_coeffs_device": [_vp, _vp, _vp],
+    "dpd_set_coeffs_device_if": [_vp, _vp, _vp, _vp],
     "dpd_set_tune": [_vp, ctypes.POINTER(dpd_tune)],
     "dpd_get_tune": [_vp, ctypes.POINTER(dpd_tune)],
     "dpd_apply": [_vp, _vp, _vp, _vp, _i64],
@@ -171,6 +172,10 @@ def dpd_set_coeffs(plan: int, coeffs_host):
 
 def dpd_set_coeffs_device(plan: int, coeffs_dev_ptr: int, stream: int):
     _check(lib().dpd_set_coeffs_device(plan, coeffs_dev_ptr, stream), "dpd_set_coeffs_device")
+
+
+def dpd_set_coeffs_device_if(plan: int, coeffs_dev_ptr: int, flag_dev_ptr: int, stream: int):
+    _check(lib().dpd_set_coeffs_device_if(plan, coeffs_dev_ptr, flag_dev_ptr, stream), "dpd_set_coeffs_device_if")
 
 
 def dpd_set_tune(plan: int, samples_per_thread=4, stage_lds=1, block=256, grid_mult=8):

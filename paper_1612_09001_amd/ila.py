@@ -69,7 +69,9 @@ class ILA:
 
     def step(self):
         """One iteration: fit the postdistorter (y / G -> z) and copy it into
-        the predistorter.  Returns the device info flag of the solve."""
+        the predistorter.  Returns the device info flag of the solve; when it
+        is not 0 (the normal equations were not positive definite) the
+        predistorter keeps its previous coefficients."""
         z, y = self.transmit()
         st = _dpd.current_stream()
         K = self.plan.K
@@ -78,7 +80,8 @@ class ILA:
                            self.b.data_ptr())
         _dpd.dpd_ls_solve(st, K, self.A.data_ptr(), self.b.data_ptr(), self.ridge, self.sws.data_ptr(),
                           self.sws_bytes, self.h.data_ptr(), self.info.data_ptr())
-        _dpd.dpd_set_coeffs_device(self.plan.handle, self.h.data_ptr(), st)
+        # copied into the predistorter only when the solve succeeded (info == 0)
+        _dpd.dpd_set_coeffs_device_if(self.plan.handle, self.h.data_ptr(), self.info.data_ptr(), st)
         return self.info
 
     def nmse_db(self) -> float:
