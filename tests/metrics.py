@@ -8,6 +8,12 @@ import numpy as np
 
 NMSE_DB_MAX = -110.0
 MAX_REL_MAX = 2e-5
+# Coefficient gradients (K entries): each entry within 1e-5 of its FP64 value,
+# relative to max(|g_k|, rms(g)) (the floor keeps entries that nearly cancel
+# from demanding more than FP32 accumulation gives), and the relative L2 error
+# of the whole vector within 1e-5.
+DCOEF_ENTRY_MAX = 1e-5
+DCOEF_REL_MAX = 1e-5
 
 
 def nmse_db(zhat, z) -> float:
@@ -36,3 +42,25 @@ def assert_parity(zhat, z, what=""):
     mr = max_rel(zhat, z)
     assert nm <= NMSE_DB_MAX and mr <= MAX_REL_MAX, "%s: NMSE %.1f dB, max rel %.3g" % (what, nm, mr)
     return nm, mr
+
+
+def entry_err(g, ref) -> float:
+    """max_k |g_k - ref_k| / max(|ref_k|, rms(ref))."""
+    g = np.asarray(g, dtype=np.complex128).reshape(-1)
+    ref = np.asarray(ref, dtype=np.complex128).reshape(-1)
+    if ref.size == 0:
+        return 0.0
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    den = np.maximum(np.abs(ref), rms)
+    den = np.where(den > 0, den, 1.0)
+    return float(np.max(np.abs(g - ref) / den))
+
+
+def assert_dcoef(g, ref, what="", entry_max=DCOEF_ENTRY_MAX, rel_max=DCOEF_REL_MAX):
+    """Coefficient-gradient parity: every entry and the vector norm."""
+    g = np.asarray(g, dtype=np.complex128).reshape(-1)
+    ref = np.asarray(ref, dtype=np.complex128).reshape(-1)
+    ee = entry_err(g, ref)
+    rel = float(np.linalg.norm(g - ref) / max(np.linalg.norm(ref), 1e-300))
+    assert ee <= entry_max and rel <= rel_max, "%s: dcoef entry err %.3g, rel L2 %.3g" % (what, ee, rel)
+    return ee, rel

@@ -125,13 +125,35 @@ def test_invalid_descriptors(torch, mods):
                      dict(main_orders=[1], conj_orders=[], L=2, **{"in": x[60:70], "out": x[:10], "n": 10, "coeffs": c})])
 
 
-def test_config4_full_sampled(torch, mods, orc):
-    """256 streams, lengths U[2^14, 2^20], P_max in {5,7,9}, L in {2..8}."""
+@pytest.fixture(scope="module")
+def config4(torch, mods, orc):
+    """The 256-stream workload and its FP64 oracle outputs (computed once)."""
     dpd, batch = mods
     wl = batch.BatchWorkload(signals.batch_specs(), config_id=4)
-    b = batch.Batch(wl.streams())
+    refs = []
+    for s, (n, pmax, L) in enumerate(wl.specs):
+        orders = signals.odd_orders(pmax)
+        refs.append(orc.forward(wl.stream_input(s), orders, orders, L, wl.coeffs_host[s]))
+    return wl, refs
+
+
+# the library's default launch shape and the benchmark's autotuned ones
+@pytest.mark.parametrize("tune", [None, {"samples_per_thread": 8, "grid_mult": 16},
+                                  {"samples_per_thread": 8, "grid_mult": 4},
+                                  {"samples_per_thread": 4, "grid_mult": 8}],
+                         ids=["default", "S8_g16", "S8_g4", "S4_g8"])
+def test_config4_every_stream_full(torch, mods, config4, tune):
+    """256 streams, lengths U[2^14, 2^20], P_max in {5,7,9}, L in {2..8}: every
+    output of every stream against the FP64 oracle."""
+    dpd, batch = mods
+    wl, refs = config4
+    b = batch.Batch(wl.streams(), tune=tune)
+    S = (tune or {}).get("samples_per_thread", 8)
     ntiles, nblocks = b.info()
-    assert ntiles == sum((n + 511) // 512 for n, _, _ in wl.specs)   # chunks of 64 * 8 samples
+    assert ntiles == sum((n + 64 * S - 1) // (64 * S) for n, _, _ in wl.specs)
+    wl.z.fill_(complex(7.0, -7.0))
     b.apply()
     z = wl.z.cpu().numpy()
-    _check_streams(wl, z, orc, count=2000)
+    for s, (n, _, _) in enumerate(wl.specs):
+        assert_parity(z[wl.offsets[s]:wl.offsets[s] + n], refs[s], "stream %d %s" % (s, tune))
+    b.close()

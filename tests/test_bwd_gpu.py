@@ -3,12 +3,10 @@ finite differences on the GPU, and bitwise run-to-run determinism."""
 import numpy as np
 import pytest
 
-from metrics import assert_parity, nmse_db
+from metrics import assert_dcoef, assert_parity, nmse_db
 from paper_1612_09001_amd import signals
 
 pytestmark = pytest.mark.gpu
-
-DCOEF_REL_MAX = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -32,10 +30,6 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).cuda()
 
 
-def _rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
-
-
 def _check(torch, dpd, orc, x, G, mo, co, L, h, rows=None, what=""):
     plan = dpd.Plan(mo, co, L, h)
     xd, gd = _dev(torch, x), _dev(torch, G)
@@ -53,8 +47,7 @@ def _check(torch, dpd, orc, x, G, mo, co, L, h, rows=None, what=""):
             rx[r] = a
             rc = rc + b
     assert_parity(gx.reshape(-1), rx.reshape(-1), "dx " + what)
-    rel = _rel(gc, rc)
-    assert rel <= DCOEF_REL_MAX, "dcoef %s rel %.3g" % (what, rel)
+    assert_dcoef(gc, rc, "dcoef " + what)
     return gx, gc
 
 
@@ -103,7 +96,7 @@ def test_partial_requests(torch, dpd, orc):
     assert_parity(gx.cpu().numpy(), rx)
     gx, gc = plan.backward(_dev(torch, x), _dev(torch, G), want_dx=False)
     assert gx is None
-    assert _rel(gc.cpu().numpy(), rc) <= DCOEF_REL_MAX
+    assert_dcoef(gc.cpu().numpy(), rc, "dcoef only")
 
 
 def test_empty_gives_zero_gradient(torch, dpd):
@@ -177,7 +170,7 @@ def test_autograd_function(torch, dpd, orc):
         rx, b = orc.backward(x[r], mo, co, L, h, W[r])
         rc = rc + b
         assert nmse_db(xt.grad[r].cpu().numpy(), rx) <= -110
-    assert _rel(ct.grad.cpu().numpy(), rc) <= DCOEF_REL_MAX
+    assert_dcoef(ct.grad.cpu().numpy(), rc, "DPDFunction")
 
 
 def test_config5_shape_full(torch, dpd, orc):

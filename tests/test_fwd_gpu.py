@@ -187,17 +187,45 @@ def test_device_coeffs_match_host(torch, dpd):
     assert np.array_equal(z1, z2) and np.array_equal(z1, z3)
 
 
-def _sample_idx(n, T, rng, count=1 << 15):
-    edges = []
-    for t0 in (0, T, 2 * T, n - T, n // 2 - (n // 2) % T):
-        edges.extend(range(max(0, t0 - 9), min(n, t0 + 9)))
-    edges.extend(range(n - 9, n))
-    idx = np.concatenate([np.array(edges), rng.integers(0, n, count)])
-    return np.unique(idx)
+def test_device_coeff_calls_leave_plan_coeffs(torch, dpd, orc):
+    """dpd_apply_coeffs and dpd_backward with device coefficients use the
+    plan's second table: a later dpd_apply still filters with the plan's own
+    coefficients."""
+    mo, co, L = [1, 3, 5], [1, 3], 4
+    h1 = signals.aph_coeffs(mo, co, L, config_id=97)
+    h2 = signals.aph_coeffs(mo, co, L, config_id=98)
+    x = signals.ofdm_16qam(30001, config_id=97)
+    xd = _dev(torch, x)
+    plan = dpd.Plan(mo, co, L, h1)
+    z2 = _host(plan.apply_coeffs(_dev(torch, h2), xd))
+    assert_parity(z2, orc.forward(x, mo, co, L, h2), "apply_coeffs")
+    z1 = _host(plan.apply(xd))
+    assert_parity(z1, orc.forward(x, mo, co, L, h1), "plan coefficients after apply_coeffs")
+    plan.backward(xd, xd, coeffs=_dev(torch, h2))
+    z1b = _host(plan.apply(xd))
+    assert np.array_equal(z1, z1b), "plan coefficients after backward with device coefficients"
 
 
-def test_config2_full_size_sampled(torch, dpd, orc):
-    """N = 2^24 in the launch shape the benchmark times; sampled outputs."""
+def test_conditional_device_coeffs(torch, dpd, orc):
+    """dpd_set_coeffs_device_if copies only when the device flag is 0."""
+    mo, co, L = [1, 3], [1], 3
+    h1 = signals.aph_coeffs(mo, co, L, config_id=99)
+    h2 = signals.aph_coeffs(mo, co, L, config_id=100)
+    x = signals.ofdm_16qam(5000, config_id=99)
+    xd = _dev(torch, x)
+    plan = dpd.Plan(mo, co, L, h1)
+    flag = torch.tensor(3, dtype=torch.int32, device="cuda")
+    h2d = _dev(torch, h2)
+    st = dpd.current_stream()
+    dpd.dpd_set_coeffs_device_if(plan.handle, h2d.data_ptr(), flag.data_ptr(), st)
+    assert_parity(_host(plan.apply(xd)), orc.forward(x, mo, co, L, h1), "flag set: unchanged")
+    flag.zero_()
+    dpd.dpd_set_coeffs_device_if(plan.handle, h2d.data_ptr(), flag.data_ptr(), st)
+    assert_parity(_host(plan.apply(xd)), orc.forward(x, mo, co, L, h2), "flag clear: replaced")
+
+
+def test_config2_full_size(torch, dpd, orc):
+    """N = 2^24 in the launch shape the benchmark times; every output."""
     mo = co = [1, 3, 5, 7]
     L = 4
     n = 1 << 24
@@ -205,13 +233,12 @@ def test_config2_full_size_sampled(torch, dpd, orc):
     h = signals.aph_coeffs(mo, co, L, config_id=2)
     plan = dpd.Plan(mo, co, L, h)
     z = _host(plan.apply(_dev(torch, x)))
-    T = 256 * plan.get_tune()["samples_per_thread"]
-    idx = _sample_idx(n, T, np.random.default_rng(2))
-    assert_parity(z[idx], orc.forward_at(x, mo, co, L, h, idx), "config2")
+    assert_parity(z, orc.forward(x, mo, co, L, h), "config2")
 
 
-def test_config3_full_size_sampled(torch, dpd, orc):
-    """N = 2^26 two-carrier stream, I = {1..9} both branches, L = 8."""
+def test_config3_full_size(torch, dpd, orc):
+    """N = 2^26 two-carrier stream, I = {1..9} both branches, L = 8; every
+    output against the FP64 oracle."""
     mo = co = [1, 3, 5, 7, 9]
     L = 8
     n = 1 << 26
@@ -221,9 +248,8 @@ def test_config3_full_size_sampled(torch, dpd, orc):
     xd = _dev(torch, x)
     z = _host(plan.apply(xd))
     del xd
-    T = 256 * plan.get_tune()["samples_per_thread"]
-    idx = _sample_idx(n, T, np.random.default_rng(3))
-    assert_parity(z[idx], orc.forward_at(x, mo, co, L, h, idx), "config3")
+    ref = orc.forward(x, mo, co, L, h)
+    assert_parity(z, ref, "config3")
 
 
 def _table2():
