@@ -3,6 +3,7 @@ autograd step and the plain-ops autograd step against the FP64 chain."""
 import numpy as np
 import pytest
 
+from metrics import assert_dcoef
 from paper_1612_09001_amd import signals
 
 pytestmark = pytest.mark.gpu
@@ -40,7 +41,8 @@ def test_fused_gradient_matches_fp64_chain(torch, orc):
     torch.cuda.synchronize()
     E, g = opa.chain_loss_and_gradient(orc, x, ORDERS, L, h)
     assert abs(float(loss.item()) - E) <= 1e-5 * E
-    assert _rel(tr.gc.cpu().numpy(), g) <= 1e-4, _rel(tr.gc.cpu().numpy(), g)
+    # three FP32 stages (predistorter, modulator, PA), each within 1e-5
+    assert_dcoef(tr.gc.cpu().numpy(), g, "chain gradient", entry_max=1e-4, rel_max=1e-4)
 
 
 def test_three_paths_agree(torch):
@@ -105,3 +107,45 @@ def test_loss_grad_against_fp64(torch, n, off):
     g = gy.cpu().numpy()
     ref = (2 * 0.1 / n) * r
     assert np.max(np.abs(g - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+def test_gradient_learned_suppression(torch, orc):
+    """The learning workload's procedure (64 x 2^18 samples, FusedTrainer, 200
+    Adam steps from the identity) at the drive level of the indirect-learning
+    fit (RMS 0.2: at the workload's RMS 0.25 the predistorted peaks reach the
+    region above |u| ~ 0.9 where the polynomial PA of Eq. (3) stops being
+    physical, and no odd-order predistorter of this size linearizes it) with
+    Adam lr 0.03: the learned predistorter suppresses the guard-band regrowth
+    of the synthetic transmitter by more than 10 dB (section 5.2 reports > 10
+    dB on the major spurs); the GPU chain's figures before and after are within
+    0.5 dB of the FP64 chain's for the same coefficients."""
+    import oracle.ila as oila
+    from paper_1612_09001_amd import dpd, spectral
+    from paper_1612_09001_amd.pa import SyntheticPA
+    from paper_1612_09001_amd.train import FusedTrainer
+
+    rows, n = 64, 1 << 18
+    x = np.stack([signals.ofdm_16qam(n, config_id=5, stream_id=r, rms=0.2) for r in range(rows)])
+    xd = torch.from_numpy(x).cuda()
+    h0 = signals.identity_coeffs(*ORDERS, L)
+    tr = FusedTrainer(xd, *ORDERS, L, h0, lr=0.03)
+    for _ in range(200):
+        tr.step()
+    h = tr.coeffs.cpu().numpy()
+    pa = SyntheticPA()
+    row = x[0]
+
+    def gpu(hh):
+        plan = dpd.Plan(*ORDERS, L, hh)
+        _, y = pa.forward(plan.apply(xd[0].contiguous()))
+        return spectral.distortion_regrowth_db(y.cpu().numpy() / pa.gain, row)
+
+    def fp64(hh):
+        _, y = oila.transmit(orc, row, ORDERS, L, hh)
+        return spectral.distortion_regrowth_db(y[0] / oila.GAIN, row)
+
+    g0, g1 = gpu(h0), gpu(h)
+    o0, o1 = fp64(h0), fp64(h)
+    print("guard-band distortion: no DPD %.2f dB (FP64 %.2f), learned %.2f dB (FP64 %.2f)" % (g0, o0, g1, o1))
+    assert abs(g0 - o0) <= 0.5 and abs(g1 - o1) <= 0.5, (g0, o0, g1, o1)
+    assert g1 <= g0 - 10.0, (g0, g1)
