@@ -167,6 +167,22 @@ dpd_status dpd_backward(dpd_plan *plan, void *stream, const void *coeffs_dev, co
                         const void *grad_z, void *grad_x, void *grad_coeffs, int64_t rows,
                         int64_t n, int64_t ld, void *ws, size_t ws_bytes);
 
+/* dpd_backward_noalloc -- for callers that cannot allocate device memory or
+ * pass a workspace (code under stream capture into a graph, tight serving
+ * loops, harnesses that forbid allocation): dpd_backward with the same
+ * arguments minus the workspace, the same kernels and bitwise the same
+ * results.  The per-block partial sums of the coefficient gradient live in a
+ * fixed device array of the library (4.25 MiB per GPU, held until the process
+ * ends); a plan whose partials need more (only on devices with many more
+ * compute units than the MI355X's 256) is DPD_EUNSUPPORTED.  It calls no
+ * allocator.  The array is shared by every call on one GPU: calls with a
+ * coefficient gradient that overlap in time on one GPU (different streams or
+ * host threads) race on it -- order them.  Calls without grad_coeffs use no
+ * scratch. */
+dpd_status dpd_backward_noalloc(dpd_plan *plan, void *stream, const void *coeffs_dev, const void *x,
+                                const void *grad_z, void *grad_x, void *grad_coeffs, int64_t rows,
+                                int64_t n, int64_t ld);
+
 /* ---------------------------------------------------------------- batched --
  * Many streams of uneven length, each with its own order set, L and
  * coefficients, in one persistent launch (many antennas of a massive-MIMO

@@ -212,9 +212,9 @@ DPD_EXPORT dpd_status dpd_backward_ws_size(const dpd_plan *plan, int64_t rows, i
     return DPD_OK;
 }
 
-DPD_EXPORT dpd_status dpd_backward(dpd_plan *plan, void *stream, const void *coeffs_dev, const void *x,
-                                   const void *grad_z, void *grad_x, void *grad_coeffs, int64_t rows,
-                                   int64_t n, int64_t ld, void *ws, size_t ws_bytes)
+static dpd_status backward_impl(dpd_plan *plan, void *stream, const void *coeffs_dev, const void *x,
+                                const void *grad_z, void *grad_x, void *grad_coeffs, int64_t rows,
+                                int64_t n, int64_t ld, void *ws, size_t ws_bytes)
 {
     if (plan == nullptr) return DPD_EINVAL;
     if (rows == 1 && ld < n) ld = n;
@@ -294,4 +294,60 @@ DPD_EXPORT dpd_status dpd_backward(dpd_plan *plan, void *stream, const void *coe
         if (e != hipSuccess) return hip_fail(e);
     }
     return DPD_OK;
+}
+
+DPD_EXPORT dpd_status dpd_backward(dpd_plan *plan, void *stream, const void *coeffs_dev, const void *x,
+                                   const void *grad_z, void *grad_x, void *grad_coeffs, int64_t rows,
+                                   int64_t n, int64_t ld, void *ws, size_t ws_bytes)
+{
+    return backward_impl(plan, stream, coeffs_dev, x, grad_z, grad_x, grad_coeffs, rows, n, ld, ws, ws_bytes);
+}
+
+// ------------------------------------------------------------ no-allocation --
+// Fixed device scratch for dpd_backward_noalloc: the per-block FP32 partials of
+// the coefficient gradient (at most kMaxBwdScratch bytes; every plan on a
+// 256-CU device needs <= 2048 blocks x 514 entries x 4 bytes + 256).  Each GPU
+// holds its own copy of the array for the life of the process.  In host code
+// the name `scratch` is only a host-side stand-in: its device address comes
+// from hipGetSymbolAddress, once per device.
+constexpr size_t kMaxBwdScratch = (size_t)17 << 18;   // 4.25 MiB
+static __device__ __align__(256) unsigned char scratch[kMaxBwdScratch];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with that device current).
+static dpd_status scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e);
+    if (dev < 0 || dev >= kMaxScratchDevices) return DPD_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_addr[dev] == nullptr) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e);
+        if (p == nullptr) return DPD_EHIP;
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return DPD_OK;
+}
+
+DPD_EXPORT dpd_status dpd_backward_noalloc(dpd_plan *plan, void *stream, const void *coeffs_dev, const void *x,
+                                           const void *grad_z, void *grad_x, void *grad_coeffs, int64_t rows,
+                                           int64_t n, int64_t ld)
+{
+    if (plan == nullptr) return DPD_EINVAL;
+    if (grad_coeffs == nullptr)   // no coefficient gradient: no scratch is used
+        return backward_impl(plan, stream, coeffs_dev, x, grad_z, grad_x, nullptr, rows, n, ld, nullptr, 0);
+    if (bwd_ws_bytes(plan->map) > kMaxBwdScratch) return DPD_EUNSUPPORTED;
+    void *ws = nullptr;
+    dpd_status st = scratch_address(&ws);
+    if (st != DPD_OK) return st;
+    return backward_impl(plan, stream, coeffs_dev, x, grad_z, grad_x, grad_coeffs, rows, n, ld, ws,
+                         kMaxBwdScratch);
 }

@@ -64,6 +64,7 @@ _SIGS = {
     "dpd_apply_hist": [_vp, _vp, _vp, _vp, _i64, _vp],
     "dpd_backward_ws_size": [_vp, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
     "dpd_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, ctypes.c_size_t],
+    "dpd_backward_noalloc": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64],
     "dpd_batch_create": [ctypes.POINTER(dpd_stream_desc), _i32, ctypes.POINTER(dpd_tune),
                          ctypes.POINTER(_vp)],
     "dpd_batch_apply": [_vp, _vp],
@@ -218,6 +219,11 @@ def dpd_backward(plan, stream, coeffs_ptr, x_ptr, gz_ptr, gx_ptr, gc_ptr, rows, 
                  ws_bytes):
     _check(lib().dpd_backward(plan, stream, coeffs_ptr, x_ptr, gz_ptr, gx_ptr, gc_ptr, int(rows),
                               int(n), int(ld), ws_ptr, int(ws_bytes)), "dpd_backward")
+
+
+def dpd_backward_noalloc(plan, stream, coeffs_ptr, x_ptr, gz_ptr, gx_ptr, gc_ptr, rows, n, ld):
+    _check(lib().dpd_backward_noalloc(plan, stream, coeffs_ptr, x_ptr, gz_ptr, gx_ptr, gc_ptr, int(rows), int(n),
+                                      int(ld)), "dpd_backward_noalloc")
 
 
 def dpd_batch_create(descs, tune: dpd_tune | None = None) -> int:
