@@ -75,14 +75,76 @@ def traffic_from_profile(n: int):
         return None
 
 
+STATS_FILE = os.path.join(ROOT, "profiles", "dpd_fwd_n2p24_P7_L4_stats.txt")
+
+
+def kernel_ns_from_profile(n: int):
+    """Average duration (ns) of the headline kernel in the committed rocprofv3
+    --stats summary; None when the kernel sources changed since then."""
+    kv = {}
+    try:
+        with open(STATS_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+    except OSError:
+        return None
+    if kv.get("kernel_sources_sha256_16") != kernel_hash() or kv.get("n", str(n)) != str(n):
+        return None
+    try:
+        return float(kv["stats_average_ns"])
+    except (KeyError, ValueError):
+        return None
+
+
+_ORC = None
+
+
+def _oracle():
+    """The FP64 oracle (test infrastructure), loaded once for the accuracy
+    gates and the CPU baseline."""
+    global _ORC
+    if _ORC is None:
+        import oracle
+        _ORC = oracle.Oracle()
+    return _ORC
+
+
+def _metrics():
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import metrics
+    return metrics
+
+
+def gate(z_gpu, z_ref) -> dict:
+    """NMSE and max relative error of a GPU output against the FP64 oracle."""
+    m = _metrics()
+    nm, mr = m.nmse_db(z_gpu, z_ref), m.max_rel(z_gpu, z_ref)
+    return {"nmse_db": round(nm, 2), "max_rel": float("%.3g" % mr),
+            "pass": bool(nm <= m.NMSE_DB_MAX and mr <= m.MAX_REL_MAX)}
+
+
+def gate_dcoef(g_gpu, g_ref, entry_max=None, rel_max=None) -> dict:
+    m = _metrics()
+    entry_max = m.DCOEF_ENTRY_MAX if entry_max is None else entry_max
+    rel_max = m.DCOEF_REL_MAX if rel_max is None else rel_max
+    ee = m.entry_err(g_gpu, g_ref)
+    rel = float(np.linalg.norm(np.asarray(g_gpu) - g_ref) / np.linalg.norm(g_ref))
+    return {"entry_err": float("%.3g" % ee), "rel_l2": float("%.3g" % rel),
+            "pass": bool(ee <= entry_max and rel <= rel_max)}
+
+
+def _timed(fn):
+    t0 = time.perf_counter()
+    r = fn()
+    return r, time.perf_counter() - t0
+
+
 def cpu_baseline(x_host, z_gpu, mo, co, L, h):
     """FP64 oracle on the host cores over the whole headline workload (median
     of 3); also gates the GPU output against it."""
-    import oracle
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from metrics import max_rel, nmse_db
-
-    orc = oracle.Oracle()
+    orc = _oracle()
     times = []
     z = None
     for _ in range(3):
@@ -91,8 +153,7 @@ def cpu_baseline(x_host, z_gpu, mo, co, L, h):
         times.append(time.perf_counter() - t)
     t = float(np.median(times))
     n = x_host.size
-    acc = {"nmse_db": round(nmse_db(z_gpu, z), 2), "max_rel": float("%.3g" % max_rel(z_gpu, z))}
-    acc["pass"] = bool(acc["nmse_db"] <= -110.0 and acc["max_rel"] <= 2e-5)
+    acc = gate(z_gpu, z)
     threads = orc.threads()
     # the same oracle on one thread, over the first 2^21 samples
     m = min(n, 1 << 21)
@@ -111,6 +172,10 @@ def cpu_baseline(x_host, z_gpu, mo, co, L, h):
             "single_thread_sample": "first %d samples of the same workload, one thread, median of 3" % m,
             "cpu_model": _cpu_model()}
     return base, acc
+
+
+# oracle timings of the secondary workloads, filled in by their legs
+CPU_EXTRA = {}
 
 
 def _cpu_model() -> str:
@@ -192,7 +257,19 @@ def leg_config1(torch, dpd, signals, steps=2000, graph_len=100, singles=200):
         torch.cuda.current_stream().synchronize()
         lat.append(time.perf_counter() - t0)
     lat_us = float(np.median(lat)) * 1e6
+    orc = _oracle()
+    x_host = x.cpu().numpy()
+    h = signals.aph_coeffs(orders, orders, L, config_id=1)
+    ref = orc.forward(x_host, orders, orders, L, h)
+    reps_cpu = []
+    for _ in range(20):
+        t0 = time.perf_counter()
+        orc.forward(x_host, orders, orders, L, h)
+        reps_cpu.append(time.perf_counter() - t0)
+    CPU_EXTRA["config1_forward"] = {"msamples_per_s": round(n / float(np.median(reps_cpu)) / 1e6, 2),
+                                    "sample": "the whole N=65536 stream, median of 20", "cores": orc.threads()}
     return {"workload": "single stream N=65536, orders {1,3,5,7} main+conj, L=4, DC (launch-bound)",
+            "accuracy": gate(z.cpu().numpy(), ref),
             "tune": tune, "back_to_back_us_per_apply_default_tune": round(default_ms * 1e3, 2),
             "back_to_back_us_per_apply": round(launch_ms * 1e3, 2),
             "back_to_back_msamples_per_s": round(n / (launch_ms * 1e-3) / 1e6, 1),
@@ -217,8 +294,15 @@ def leg_config3(torch, dpd, signals, steps=50):
     flops = 8 * len(orders) * L + 3           # widely-linear FIR + |x|^2 per sample
     tfl = flops * n / (kmean * 1e-3) / 1e12
     gbs = BYTES_PER_SAMPLE * n / (kmean * 1e-3) / 1e9
+    z_last = zs[(steps - 1) % len(xs)].cpu().numpy()
     del xs, zs
-    return {"workload": "two-carrier N=2^26, orders {1,3,5,7,9} main+conj, L=8, DC",
+    orc = _oracle()
+    ref, t_cpu = _timed(lambda: orc.forward(x_host, orders, orders, L, h))
+    CPU_EXTRA["config3_forward"] = {"msamples_per_s": round(n / t_cpu / 1e6, 2), "cores": orc.threads(),
+                                    "sample": "the whole 2^26-sample two-carrier stream, one run"}
+    acc = gate(z_last, ref)
+    del ref, z_last
+    return {"workload": "two-carrier N=2^26, orders {1,3,5,7,9} main+conj, L=8, DC", "accuracy": acc,
             "msamples_per_s": round(n * steps / wall / 1e6, 1), "kernel_ms": round(kmean, 4),
             "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
             "valu_tflops": round(tfl, 2), "flops_per_sample": flops,
@@ -247,6 +331,18 @@ def leg_config4(torch, dpd, signals, reps=20):
         b.apply_each()
     t_graph_each = autotune.time_us(ge.replay, iters=reps)
     gbs = BYTES_PER_SAMPLE * total / (t_graph * 1e-6) / 1e9
+    # every output of every stream (from the last graph replay) against the oracle
+    torch.cuda.synchronize()
+    z = wl.z.cpu().numpy()
+    orc = _oracle()
+    worst = None
+    for s_, (n_, pmax, L_) in enumerate(wl.specs):
+        orders_ = signals.odd_orders(pmax)
+        g = gate(z[wl.offsets[s_]:wl.offsets[s_] + n_],
+                 orc.forward(wl.stream_input(s_), orders_, orders_, L_, wl.coeffs_host[s_]))
+        if worst is None or g["nmse_db"] > worst["nmse_db"]:
+            worst = dict(g, stream=s_)
+        worst["pass"] = bool(worst["pass"] and g["pass"])
     # widely-linear FIR + |x|^2 per sample, per stream (both branches hold orders 1..P_max)
     flops = sum(n * (8 * ((pmax + 1) // 2) * L + 3) for n, pmax, L in wl.specs)
     t_hbm = BYTES_PER_SAMPLE * total / (HBM_PEAK_GBS * 1e9) * 1e6
@@ -257,6 +353,7 @@ def leg_config4(torch, dpd, signals, reps=20):
                     n * (8 * ((pmax + 1) // 2) * L + 3) / (VALU_FP32_NONPACKED_TFLOPS * 1e12))
                 for n, pmax, L in wl.specs) * 1e6
     return {"workload": "256 streams, n~U[2^14,2^20] (seeded), P_max in {5,7,9}, L in {2..8}, conj+DC",
+            "accuracy_worst_stream": worst,
             "samples": total, "tune": tune, "chunks_blocks": list(b.info()),
             "persistent_graph_us": round(t_graph, 1), "persistent_us": round(t_direct, 1),
             "per_stream_launches_us": round(t_each, 1), "per_stream_graph_us": round(t_graph_each, 1),
@@ -289,7 +386,13 @@ def leg_backward(torch, dpd, signals, steps=50):
     # dx: transposed filter 8*NI*L + basis Jacobian ~12*NI; dcoef: outer products 8*NI*L + basis 2*NI
     flops = 16 * ni * L + 14 * ni
     nbytes = 24 * n                         # x and G read, dx written
+    orc = _oracle()
+    (rx, rc), t_cpu = _timed(lambda: orc.backward(x.cpu().numpy(), orders, orders, L, h, g.cpu().numpy()))
+    CPU_EXTRA["backward"] = {"msamples_per_s": round(n / t_cpu / 1e6, 2), "cores": orc.threads(),
+                             "sample": "dx and dcoef of the whole 2^24-sample stream, one run"}
+    acc = {"dx": gate(gx.cpu().numpy(), rx), "dcoef": gate_dcoef(gc.cpu().numpy(), rc)}
     return {"workload": "adjoint of the headline: N=2^24, orders {1,3,5,7} main+conj, L=4; dx and dcoef",
+            "accuracy": acc,
             "kernel_ms": round(kmean, 4), "msamples_per_s": round(n / (kmean * 1e-3) / 1e6, 1),
             "hbm_frac": round(nbytes / (kmean * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "flops_per_sample": flops,
             "valu_frac_nonpacked": round(flops * n / (kmean * 1e-3) / 1e12 / VALU_FP32_NONPACKED_TFLOPS, 4)}
@@ -314,9 +417,12 @@ def leg_table2(torch, dpd, signals, steps=200):
         torch, lambda i: dpd.dpd_apply(plan.handle, st, ptrs[i][0], ptrs[i][1], n), len(xs), steps, 200)
     msps = n / (kmean * 1e-3) / 1e6
     gbs = BYTES_PER_SAMPLE * n / (kmean * 1e-3) / 1e9
+    z_last = zs[(steps - 1) % len(xs)].cpu().numpy()
     del xs, zs
     best = max(PAPER_TABLE4_MSPS.values())
+    acc = gate(z_last, _oracle().forward(x_host, mo, co, L, signals.aph_coeffs(mo, co, L, config_id=2)))
     return {"workload": "Table 2 configuration: orders {1,3,5} main, {1,3} conjugate, L=5, DC; N=2^24",
+            "accuracy": acc,
             "kernel_ms": round(kmean, 4), "msamples_per_s": round(msps, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "tune": plan.get_tune(),
             "paper_table4_msamples_per_s": PAPER_TABLE4_MSPS,
@@ -382,6 +488,12 @@ def leg_ingest(torch, dpd, signals, reps=3):
     t = float(np.median(ts))
     out["zero_copy"] = {"ms": round(t * 1e3, 2), "msamples_per_s": round(n / t / 1e6, 1),
                         "host_link_gbs_each_way": round(8 * n / t / 1e9, 2)}
+    ref = _oracle().forward(xh.numpy(), orders, orders, L, signals.aph_coeffs(orders, orders, L, config_id=1))
+    out["accuracy_zero_copy"] = gate(zh.numpy(), ref)
+    pipe = ingest.HostPipeline(plan, chunk=1 << 22)
+    zh.fill_(0)
+    pipe.run(xh, zh)
+    out["accuracy_pipeline"] = gate(zh.numpy(), ref)
     return out
 
 
@@ -406,10 +518,14 @@ def leg_ls(torch, dpd, signals, reps=5):
     st = dpd.current_stream()
     out = {"workload": "normal equations of the K=33 headline basis; Cholesky solve; indirect learning",
            "K": K, "real_features": D, "useful_flops_per_sample": useful, "mfma_bf16_flops_per_sample": issued}
+    m = _metrics()
+    orc = _oracle()
     for lg in (20, 24):
         n = 1 << lg
-        y = torch.from_numpy(signals.ofdm_16qam(n, config_id=1)).cuda()
-        t = torch.from_numpy(signals.ofdm_16qam(n, config_id=1, stream_id=2)).cuda()
+        y_host = signals.ofdm_16qam(n, config_id=1)
+        t_host = signals.ofdm_16qam(n, config_id=1, stream_id=2)
+        y = torch.from_numpy(y_host).cuda()
+        t = torch.from_numpy(t_host).cuda()
         A = torch.empty((K, K), dtype=torch.complex128, device="cuda")
         b = torch.empty(K, dtype=torch.complex128, device="cuda")
         wsb = dpd.dpd_ls_ws_size(plan.handle, 1, n)
@@ -421,6 +537,15 @@ def leg_ls(torch, dpd, signals, reps=5):
         out["normal_2^%d_useful_tflops" % lg] = round(useful * n / (us * 1e-6) / 1e12, 2)
         out["normal_2^%d_mfma_bf16_tflops" % lg] = round(issued * n / (us * 1e-6) / 1e12, 2)
         out["normal_2^%d_mfma_bf16_frac" % lg] = round(issued * n / (us * 1e-6) / 1e12 / MFMA_BF16_TFLOPS, 4)
+        (Ar, br), t_cpu = _timed(lambda: orc.ls_normal(y_host, orders, orders, L, t_host))
+        ea, eb, ma, mb = m.ls_errors(A.cpu().numpy(), b.cpu().numpy(), Ar, br,
+                                     float(np.sum(np.abs(t_host.astype(np.complex128)) ** 2)))
+        out["normal_2^%d_accuracy" % lg] = {"A_scaled_frob": float("%.3g" % ea), "b_scaled_frob": float("%.3g" % eb),
+                                            "A_scaled_entry_max": float("%.3g" % ma),
+                                            "b_scaled_entry_max": float("%.3g" % mb),
+                                            "pass": bool(max(ea, eb, ma, mb) <= m.LS_REL_MAX)}
+        CPU_EXTRA["ls_normal_2^%d" % lg] = {"msamples_per_s": round(n / t_cpu / 1e6, 3), "cores": orc.threads(),
+                                           "sample": "the whole 2^%d-sample fit, one run" % lg}
         del y, t, ws
     h, info = dpd.ls_solve(A, b, 1e-9)
     swsb = dpd.dpd_ls_solve_ws_size(K)
@@ -456,6 +581,28 @@ def leg_ls(torch, dpd, signals, reps=5):
     out["ila_nmse_db_iters_0_to_3"] = [round(v, 2) for v in e]
     out["guard_band_distortion_db_after_3_iters"] = regrowth()
     out["ila_solve_info"] = int(est.info.item())
+    # the same three iterations composed from FP64 oracle calls
+    import oracle.ila as oila
+    ref, _ = oila.run(orc, xh, (orders, orders), L, signals.identity_coeffs(orders, orders, L), 3, ridge=est.ridge)
+    out["ila_fp64_nmse_db_iters_0_to_3"] = [round(v, 2) for v in ref]
+    out["ila_max_abs_diff_db_vs_fp64"] = round(float(np.max(np.abs(np.array(e) - np.array(ref)))), 3)
+    # the non-contiguous two-carrier signal (gap between the carriers)
+    x2h = signals.two_carrier(1 << 18, config_id=3, stream_id=5, rms=0.2)
+    est2 = ila.ILA(torch.from_numpy(x2h).cuda(), orders, orders, L)
+
+    def regrowth2():
+        _, y2 = est2.transmit()
+        return round(spectral.distortion_regrowth_db(y2.cpu().numpy() / est2.pa.gain, x2h,
+                                                     bands=spectral.TWO_CARRIER), 2)
+
+    out["two_carrier_gap_distortion_db_no_dpd"] = regrowth2()
+    for _ in range(3):
+        est2.step()
+    out["two_carrier_gap_distortion_db_after_3_iters"] = regrowth2()
+    out["two_carrier_ila_solve_info"] = int(est2.info.item())
+    _, y2 = oila.transmit(orc, x2h, (orders, orders), L, est2.h.cpu().numpy())
+    out["two_carrier_gap_distortion_db_after_3_iters_fp64_chain"] = round(
+        spectral.distortion_regrowth_db(y2[0] / oila.GAIN, x2h, bands=spectral.TWO_CARRIER), 2)
     return out
 
 
@@ -487,7 +634,24 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
         ms = [a.elapsed_time(b) for a, b in ms]
         return ms, [float(v.item()) for v in losses]
 
-    fused_ms, fused_loss = run(FusedTrainer(xd, orders, orders, L, h0), steps)
+    # the fused step's loss and coefficient gradient at the identity against the FP64 chain (all 64 rows)
+    import oracle.pa as opa
+    tr0 = FusedTrainer(xd, orders, orders, L, h0, lr=0.0)
+    loss0 = float(tr0.step().item())
+    gc0 = tr0.gc.cpu().numpy()
+    orc = _oracle()
+    (E_ref, g_ref), t_cpu = _timed(lambda: opa.chain_loss_and_gradient(orc, x, (orders, orders), L, h0))
+    CPU_EXTRA["config5_chain_gradient"] = {"msamples_per_s": round(rows * n / t_cpu / 1e6, 3), "cores": orc.threads(),
+                                           "sample": "loss and coefficient gradient of the whole 64 x 2^18 batch "
+                                                     "through the FP64 chain, one run"}
+    acc = {"loss_rel": float("%.3g" % (abs(loss0 - E_ref) / E_ref)),
+           "gradient": gate_dcoef(gc0, g_ref, entry_max=1e-4, rel_max=1e-4)}
+    acc["pass"] = bool(acc["loss_rel"] <= 1e-5 and acc["gradient"]["pass"])
+    del tr0
+    trf = FusedTrainer(xd, orders, orders, L, h0)
+    fused_ms, fused_loss = run(trf, steps)
+    h_fused = trf.coeffs.cpu().numpy()
+    del trf
     stage_ms, stage_loss = run(FusedTrainer(xd, orders, orders, L, h0, fused_transmitter=False), 50)
     auto_ms, auto_loss = run(AutogradTrainer(xd, orders, orders, L, h0), plain_steps)
     plain_ms, plain_loss = run(PlainTrainer(xd, orders, orders, L, h0), plain_steps)
@@ -495,7 +659,34 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
     agree = float(np.max(np.abs(np.array(plain_loss[:k]) - np.array(fused_loss[:k])) /
                          np.array(fused_loss[:k])))
     med = lambda v: float(np.median(v[10:] if len(v) > 12 else v[2:]))
+    # suppression after the gradient-learned predistorter: the same procedure at
+    # the indirect-learning drive level (RMS 0.2) with Adam lr 0.03
+    from paper_1612_09001_amd import spectral
+    from paper_1612_09001_amd.pa import SyntheticPA
+    import oracle.ila as oila
+    x2 = np.stack([signals.ofdm_16qam(n, config_id=5, stream_id=r, rms=0.2) for r in range(rows)])
+    x2d = torch.from_numpy(x2).cuda()
+    tr2 = FusedTrainer(x2d, orders, orders, L, h0, lr=0.03)
+    for _ in range(steps):
+        tr2.step()
+    h2 = tr2.coeffs.cpu().numpy()
+    spa = SyntheticPA()
+
+    def guard(hh, xx=x2d, xh=x2[0]):
+        pl = dpd.Plan(orders, orders, L, hh)
+        _, yy = spa.forward(pl.apply(xx[0].contiguous()))
+        return round(spectral.distortion_regrowth_db(yy.cpu().numpy() / spa.gain, xh), 2)
+
+    _, y64 = oila.transmit(orc, x2[0], (orders, orders), L, h2)
+    sup = {"workload": "64x2^18 OFDM-like at RMS 0.2, the same 200 Adam steps with lr 0.03",
+           "guard_band_distortion_db_no_dpd": guard(h0), "guard_band_distortion_db_learned": guard(h2),
+           "guard_band_distortion_db_learned_fp64_chain": round(
+               spectral.distortion_regrowth_db(y64[0] / oila.GAIN, x2[0]), 2),
+           "at_rms_0.25_lr_1e-3": {"guard_band_distortion_db_no_dpd": guard(h0, xd, x[0]),
+                                   "guard_band_distortion_db_learned": guard(h_fused, xd, x[0])}}
+    del tr2, x2d
     return {"workload": "64x2^18 OFDM-like, DPD {1,3,5,7} main+conj L=6, synthetic PA, Adam 1e-3",
+            "accuracy_step0": acc, "suppression": sup,
             "grad_step_ms_fused": round(med(fused_ms), 4),
             "grad_step_ms_fused_transmitter_per_stage": round(med(stage_ms), 4),
             "per_stage_vs_fused_loss_rel_max_first_50": float("%.3g" % float(np.max(
@@ -503,6 +694,7 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
             "grad_step_ms_autograd_dpdfunction": round(med(auto_ms), 4),
             "grad_step_ms_plain_ops_autograd": round(med(plain_ms), 4),
             "speedup_vs_plain_ops": round(med(plain_ms) / med(fused_ms), 2),
+            "speedup_vs_autograd_dpdfunction": round(med(auto_ms) / med(fused_ms), 2),
             "loss_db_step0": round(10 * np.log10(fused_loss[0]), 2),
             "loss_db_final": round(10 * np.log10(fused_loss[-1]), 2), "steps": steps,
             "plain_vs_fused_loss_rel_max_first_%d" % k: float("%.3g" % agree)}
@@ -576,12 +768,18 @@ def main():
     # then rewrite every output)
     _, copy_ms = _time_launches(torch, lambda i: zs[i].copy_(xs[i]), nbuf, min(args.steps, 200), 20)
     copy_gbs = BYTES_PER_SAMPLE * n / (copy_ms * 1e-3) / 1e9
+    # the forward kernel's own memory walk without the filter (dpd_copy): the
+    # practical ceiling of this access pattern
+    _, walk_ms = _time_launches(torch, lambda i: dpd.dpd_copy(stream, ptrs[i][0], ptrs[i][1], n), nbuf,
+                                min(args.steps, 500), 50)
+    walk_gbs = BYTES_PER_SAMPLE * n / (walk_ms * 1e-3) / 1e9
     wall, kern_ms = _time_launches(
         torch, lambda i: dpd.dpd_apply(handle, stream, ptrs[i][0], ptrs[i][1], n), nbuf,
         args.steps, 1)
     ms_per_step = wall * 1e3 / args.steps
     value = n * args.steps / wall / 1e6
     achieved = BYTES_PER_SAMPLE * n / (kern_ms * 1e-3) / 1e9
+    prof_ns = kernel_ns_from_profile(n)
 
     out = {
         "metric": METRIC,
@@ -604,8 +802,14 @@ def main():
                      "traffic": traffic_from_profile(n),
                      "kernel_ms": round(kern_ms, 5),
                      "algorithmic_bytes_per_launch": BYTES_PER_SAMPLE * n,
+                     "frac_wall": round(BYTES_PER_SAMPLE * n / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "frac_rocprof": (round(BYTES_PER_SAMPLE * n / (prof_ns * 1e-9) / 1e9 / HBM_PEAK_GBS, 4)
+                                      if prof_ns else None),
+                     "rocprof_kernel_us": round(prof_ns / 1e3, 2) if prof_ns else None,
                      "runtime_copy_gbs": round(copy_gbs, 1),
-                     "frac_of_runtime_copy": round(achieved / copy_gbs, 4)},
+                     "frac_of_runtime_copy": round(achieved / copy_gbs, 4),
+                     "copy_walk_gbs": round(walk_gbs, 1), "copy_walk_us": round(walk_ms * 1e3, 2),
+                     "frac_of_copy_walk": round(achieved / walk_gbs, 4)},
     }
     z_last = zs[(args.steps - 1) % nbuf]
     if not args.main_only:
@@ -621,6 +825,8 @@ def main():
         out["secondary"] = sec
     if not args.no_cpu:
         base, acc = cpu_baseline(x_host, z_last.cpu().numpy(), mo, co, L, h)
+        if CPU_EXTRA:
+            base["other_workloads"] = CPU_EXTRA
         out["cpu_baseline"] = base
         out["accuracy"] = acc
     print(json.dumps(out), flush=True)

@@ -321,6 +321,14 @@ dpd_status dpd_ls_solve_ws_size(int32_t K, size_t *bytes);
 dpd_status dpd_ls_solve(void *stream, int32_t K, const void *A, const void *b, double ridge, void *ws,
                         size_t ws_bytes, void *h, void *info);
 
+/* ------------------------------------------------------------ measurement --
+ * dpd_copy -- out[t] = in[t] for t = 0..n-1 (complex64, device, 16-byte
+ * aligned, not overlapping) with the memory walk of the forward kernel and
+ * none of its arithmetic: the practical HBM ceiling of that walk, which the
+ * benchmark reports beside the filter's rate (not part of the paper's
+ * method).  Asynchronous on `stream`; allocates nothing. */
+dpd_status dpd_copy(void *stream, const void *in, void *out, int64_t n);
+
 /* ------------------------------------------------------------------- misc -- */
 const char *dpd_status_string(dpd_status status);
 int dpd_last_hip_error(void);

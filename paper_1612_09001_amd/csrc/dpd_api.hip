@@ -181,6 +181,53 @@ __global__ void hist_update_kernel(const float2 *__restrict__ in, int64_t n, flo
     if (i < Lm1) hist[i] = v;
 }
 
+// ------------------------------------------------------- streaming copy ---
+// The forward kernel's memory walk without the filter (measurement of the
+// practical HBM ceiling of that walk): persistent waves, wave g copies chunks
+// g, g + nw, ... of 512 samples with one chunk of register prefetch and
+// nontemporal 16-byte loads and stores (1 KiB per instruction); the last
+// n mod 512 samples one per lane after the walk.
+__global__ void __launch_bounds__(kBlock) copy_walk_kernel(const float2 *__restrict__ in, float2 *__restrict__ out,
+                                                          int64_t n)
+{
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    constexpr int C = 512, NV = 4;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t total = n / C;
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t gw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * (kBlock / 64) + wv;
+    auto ld = [&](v4 (&r)[NV], int64_t c) {
+        const v4 *x4 = reinterpret_cast<const v4 *>(in + c * C);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) r[i] = __builtin_nontemporal_load(x4 + lane + 64 * i);
+    };
+    auto st = [&](const v4 (&r)[NV], int64_t c) {
+        v4 *z4 = reinterpret_cast<v4 *>(out + c * C);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) __builtin_nontemporal_store(r[i], z4 + lane + 64 * i);
+    };
+    if (gw < total) {
+        v4 A[NV], B[NV];
+        int64_t c = gw;
+        ld(A, c);
+        for (; c + 2 * nw < total; c += 2 * nw) {
+            ld(B, c + nw);
+            st(A, c);
+            ld(A, c + 2 * nw);
+            st(B, c + nw);
+        }
+        if (c + nw < total) {
+            ld(B, c + nw);
+            st(A, c);
+            st(B, c + nw);
+        } else {
+            st(A, c);
+        }
+    }
+    for (int64_t m = total * C + gw * 64 + lane; m < n; m += nw * 64) out[m] = in[m];
+}
+
 // --------------------------------------------------------------- tables ---
 
 // Compute units of the current device (cached per device id; concurrent
@@ -445,6 +492,21 @@ DPD_EXPORT dpd_status dpd_apply_hist(dpd_plan *plan, void *stream, const void *i
     if (st != DPD_OK || Lm1 == 0) return st;
     hipLaunchKernelGGL(hist_update_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream,
                        (const float2 *)in, n, (float2 *)hist, Lm1);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DPD_OK : hip_fail(e);
+}
+
+DPD_EXPORT dpd_status dpd_copy(void *stream, const void *in, void *out, int64_t n)
+{
+    if (n < 0) return DPD_EINVAL;
+    if (n == 0) return DPD_OK;
+    if (in == nullptr || out == nullptr || (uintptr_t)in % 16 != 0 || (uintptr_t)out % 16 != 0) return DPD_EINVAL;
+    if (overlap(in, (size_t)n * 8, out, (size_t)n * 8)) return DPD_EINVAL;
+    const int64_t want = (int64_t)num_cus() * 2;      // the forward kernel's persistent grid
+    const int64_t need = (n / 512 + 3) / 4;
+    const int64_t grid = std::max<int64_t>(1, std::min(want, need));
+    hipLaunchKernelGGL(copy_walk_kernel, dim3((uint32_t)grid), dim3(kBlock), 0, (hipStream_t)stream,
+                       (const float2 *)in, (float2 *)out, n);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? DPD_OK : hip_fail(e);
 }

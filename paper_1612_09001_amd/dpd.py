@@ -82,6 +82,7 @@ _SIGS = {
     "dpd_ls_normal": [_vp, _vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, _vp, ctypes.c_size_t, _vp, _vp],
     "dpd_ls_solve_ws_size": [_i32, ctypes.POINTER(ctypes.c_size_t)],
     "dpd_ls_solve": [_vp, _i32, _vp, _vp, ctypes.c_double, _vp, ctypes.c_size_t, _vp, _vp],
+    "dpd_copy": [_vp, _vp, _vp, _i64],
 }
 
 # Symbols the header declares (checked by the CPU test-suite).
@@ -291,6 +292,10 @@ def dpd_ls_ws_size(plan, rows, n) -> int:
 def dpd_ls_normal(plan, stream, y_ptr, t_ptr, rows, n, ld, y_scale, ws_ptr, ws_bytes, a_ptr, b_ptr):
     _check(lib().dpd_ls_normal(plan, stream, y_ptr, t_ptr, int(rows), int(n), int(ld), float(y_scale), ws_ptr,
                                int(ws_bytes), a_ptr, b_ptr), "dpd_ls_normal")
+
+
+def dpd_copy(stream, in_ptr, out_ptr, n):
+    _check(lib().dpd_copy(stream, in_ptr, out_ptr, int(n)), "dpd_copy")
 
 
 def dpd_ls_solve_ws_size(K) -> int:

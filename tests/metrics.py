@@ -64,3 +64,23 @@ def assert_dcoef(g, ref, what="", entry_max=DCOEF_ENTRY_MAX, rel_max=DCOEF_REL_M
     rel = float(np.linalg.norm(g - ref) / max(np.linalg.norm(ref), 1e-300))
     assert ee <= entry_max and rel <= rel_max, "%s: dcoef entry err %.3g, rel L2 %.3g" % (what, ee, rel)
     return ee, rel
+
+
+# Normal equations of the least-squares fit: errors after the diagonal scaling
+# S = diag(A)^(-1/2), where every exact entry of S A S and of S b / |t| is at
+# most 1 (Cauchy-Schwarz).
+LS_REL_MAX = 2e-5
+
+
+def ls_errors(A, b, Ar, br, t2):
+    """Relative Frobenius errors of S A S and S b, and the largest entry errors
+    of S A S and S b / |t| (t2 = sum |t|^2)."""
+    A, b, Ar, br = (np.asarray(v, dtype=np.complex128) for v in (A, b, Ar, br))
+    dg = np.abs(np.real(np.diag(Ar)))
+    d = np.where(dg > 0, 1.0 / np.sqrt(np.where(dg > 0, dg, 1.0)), 1.0)   # all-zero columns (taps past n)
+    S = np.outer(d, d)
+    ea = np.linalg.norm((A - Ar) * S) / np.linalg.norm(Ar * S)
+    eb = np.linalg.norm((b - br) * d) / np.linalg.norm(br * d)
+    ma = np.max(np.abs(A - Ar) * S)
+    mb = np.max(np.abs(b - br) * d) / np.sqrt(t2)
+    return float(ea), float(eb), float(ma), float(mb)

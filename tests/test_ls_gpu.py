@@ -5,6 +5,7 @@ and the indirect-learning loop on the synthetic PA."""
 import numpy as np
 import pytest
 
+from metrics import LS_REL_MAX, ls_errors
 from paper_1612_09001_amd import signals
 
 pytestmark = pytest.mark.gpu
@@ -21,7 +22,6 @@ pytestmark = pytest.mark.gpu
 # 8192 samples) and the four wave partials of a slab are added in FP32 before
 # the FP64 slab sum (relative error ~1e-6 for random rounding; measured
 # 2e-7..9e-7 on A and ~3e-6 on b).  2e-5 leaves a margin of 6 or more.
-LS_REL_MAX = 2e-5
 
 
 @pytest.fixture(scope="module")
@@ -45,23 +45,8 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.complex64)).cuda()
 
 
-def _scaled_errors(A, b, Ar, br, t2):
-    """Errors of A and b after the diagonal scaling S = diag(Ar)^(-1/2) (entries
-    of a polynomial basis span many decades): relative Frobenius errors of
-    S A S and S b, and the largest entry errors of S A S and of S b / |t|
-    (t2 = sum |t|^2), where every exact entry is at most 1."""
-    dg = np.abs(np.real(np.diag(Ar)))
-    d = np.where(dg > 0, 1.0 / np.sqrt(np.where(dg > 0, dg, 1.0)), 1.0)   # all-zero columns (taps past n)
-    S = np.outer(d, d)
-    ea = np.linalg.norm((A - Ar) * S) / np.linalg.norm(Ar * S)
-    eb = np.linalg.norm((b - br) * d) / np.linalg.norm(br * d)
-    ma = np.max(np.abs(A - Ar) * S)
-    mb = np.max(np.abs(b - br) * d) / np.sqrt(t2)
-    return float(ea), float(eb), float(ma), float(mb)
-
-
 def _assert_ls(A, b, Ar, br, t2, what=""):
-    ea, eb, ma, mb = _scaled_errors(A, b, Ar, br, t2)
+    ea, eb, ma, mb = ls_errors(A, b, Ar, br, t2)
     assert max(ea, eb, ma, mb) <= LS_REL_MAX, "%s: A frob %.3g, b frob %.3g, A entry %.3g, b entry %.3g" % (
         what, ea, eb, ma, mb)
 
