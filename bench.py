@@ -366,6 +366,46 @@ def leg_config4(torch, dpd, signals, reps=20):
             "speedup_vs_per_stream_graph": round(t_graph_each / t_graph, 2)}
 
 
+def leg_batch_classes(torch, dpd, signals, reps=20):
+    """The 256-stream workload class by class (the streams of one (P_max, L)
+    class as a batch of their own, in the persistent kernel), against one
+    stream of the same class and total length through the single-stream
+    kernel; for per-class counters under a profiler (one batch_kernel dispatch
+    group per class, in the printed order).  Not part of the default run."""
+    from paper_1612_09001_amd import autotune, batch
+
+    specs = signals.batch_specs()
+    wl = batch.BatchWorkload(specs, config_id=4)
+    classes = sorted({(pm, L) for _, pm, L in specs}, key=lambda c: (-(c[0] + 1) // 2 * c[1], c))
+    st = dpd.current_stream()
+    out = []
+    for pm, L in classes:
+        idx = [i for i, (_, p_, l_) in enumerate(specs) if (p_, l_) == (pm, L)]
+        streams = [wl.streams()[i] for i in idx]
+        total = int(sum(specs[i][0] for i in idx))
+        b = batch.Batch(streams, tune={"samples_per_thread": 8, "grid_mult": 16})
+        t_b = autotune.time_us(b.apply, warmup=3, iters=reps)
+        orders = signals.odd_orders(pm)
+        plan = dpd.Plan(orders, orders, L, signals.aph_coeffs(orders, orders, L, config_id=4))
+        x = torch.from_numpy(signals.ofdm_16qam(total, config_id=4, stream_id=1000 + pm * 10 + L)).cuda()
+        z = torch.empty_like(x)
+        t_s = autotune.time_us(lambda: dpd.dpd_apply(plan.handle, st, x.data_ptr(), z.data_ptr(), total),
+                               warmup=3, iters=reps)
+        ni = (pm + 1) // 2
+        fl = 8 * ni * L + 3
+        bound = max(BYTES_PER_SAMPLE * total / (HBM_PEAK_GBS * 1e9), fl * total / (VALU_FP32_NONPACKED_TFLOPS * 1e12))
+        out.append({"P_max": pm, "L": L, "streams": len(idx), "samples": total, "batch_us": round(t_b, 1),
+                    "single_stream_us": round(t_s, 1), "batch_over_single": round(t_b / t_s, 3),
+                    "bound_us": round(bound * 1e6, 1), "batch_frac_of_bound": round(bound * 1e6 / t_b, 3),
+                    "single_frac_of_bound": round(bound * 1e6 / t_s, 3)})
+        b.close()
+        del x, z
+    return {"workload": "the 256-stream batch split by (P_max, L) class", "classes": out,
+            "sum_batch_us": round(sum(c["batch_us"] for c in out), 1),
+            "sum_single_us": round(sum(c["single_stream_us"] for c in out), 1),
+            "sum_bound_us": round(sum(c["bound_us"] for c in out), 1)}
+
+
 def leg_backward(torch, dpd, signals, steps=50):
     """Adjoint of the headline forward (N = 2^24, orders {1,3,5,7} both
     branches, L = 4): input and coefficient gradients in one call."""
@@ -714,7 +754,8 @@ def main():
                     help="also run one plain device copy of the same bytes (counter calibration)")
     ap.add_argument("--only-leg", default="",
                     help="run only these secondary workloads (comma-separated: config1, config3, config4, "
-                         "backward, config5, ls, table2, ingest) and print their results, e.g. under a profiler")
+                         "backward, config5, ls, table2, ingest, batch_classes) and print their results, "
+                         "e.g. under a profiler")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: measures one GPU only; --gpus %d is not supported (the forward map, the "
@@ -726,12 +767,14 @@ def main():
     from paper_1612_09001_amd import dpd, signals
     legs = {"config1": leg_config1, "config3": leg_config3, "config4": leg_config4, "backward": leg_backward, "config5": leg_config5,
             "ls": leg_ls, "table2": leg_table2, "ingest": leg_ingest}
+    extra_legs = {"batch_classes": leg_batch_classes}
     if args.only_leg:
+        known = dict(legs, **extra_legs)
         for name in args.only_leg.split(","):
-            if name not in legs:
-                print("bench.py: unknown workload %r (known: %s)" % (name, ", ".join(legs)), file=sys.stderr)
+            if name not in known:
+                print("bench.py: unknown workload %r (known: %s)" % (name, ", ".join(known)), file=sys.stderr)
                 sys.exit(2)
-            print(json.dumps({name: legs[name](torch, dpd, signals)}), flush=True)
+            print(json.dumps({name: known[name](torch, dpd, signals)}), flush=True)
         return
 
     n = 1 << args.log2n
