@@ -270,6 +270,25 @@ dpd_status dpd_cascade_loss_grad(const dpd_plan *A, const dpd_plan *B, void *str
 dpd_status dpd_cascade_backward(const dpd_plan *A, const dpd_plan *B, void *stream, const void *z,
                                 const void *grad_y, void *grad_z, int64_t rows, int64_t n, int64_t ld);
 
+/* dpd_transmit_loss_grad -- the forward pass of the learning step in one
+ * kernel: z = D(x) (Eq. 1 with predistorter plan P and, when coeffs_dev is not
+ * NULL, the K complex64 device coefficients coeffs_dev, precombined into P's
+ * second table as in dpd_apply_coeffs), then u = A(z), y = B(u) and the loss
+ * E and dE/dy of dpd_cascade_loss_grad (rows of x, z, grad_y at stride ld).
+ * z is written for the cascade's adjoint (dpd_cascade_backward); z and grad_y
+ * are bitwise those of dpd_apply_coeffs followed by dpd_cascade_loss_grad,
+ * and E differs from it only in the order of the FP32 partial sums.  Built
+ * for A memoryless with order 1 in each branch (I/Q imbalance and LO leakage)
+ * and B with orders {1, 3, 5} and 3 taps (the PA of the learning workload),
+ * and for P with orders up to 9 and up to 8 taps: other stages are
+ * DPD_EUNSUPPORTED (run dpd_apply_coeffs and dpd_cascade_loss_grad).  x, z,
+ * grad_y: device complex64, 8-byte aligned, z and grad_y not overlapping x or
+ * each other.  ws: >= dpd_loss_ws_size bytes.  Allocates nothing. */
+dpd_status dpd_transmit_loss_grad(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream,
+                                  const void *coeffs_dev, const void *x, void *z, int64_t rows, int64_t n,
+                                  int64_t ld, float scale, float *loss_dev, void *grad_y, void *ws,
+                                  size_t ws_bytes);
+
 /* ------------------------------------------------------- least squares --
  * The paper's coefficient estimate (section 2.2, Eq. 2): with the plan's
  * basis, row m of Psi is

@@ -12,6 +12,7 @@
 #include <cmath>
 
 #include "dpd.h"
+#include "dpd_cascade.h"
 #include "dpd_internal.h"
 #include "dpd_plan.h"
 
@@ -19,7 +20,6 @@
 
 namespace dpd {
 
-constexpr int kLossBlocks = 1024;
 
 // Chunks of 2 kBlock samples: block b takes chunks b, b + grid, ... (the
 // blocks running together sweep memory in order), two samples per lane with
@@ -127,34 +127,6 @@ struct CasParams {
     int vec;                 // rows start 16-byte aligned: whole quads use 16-byte accesses
 };
 
-constexpr int kCasTA = 4 * kMaxNI + 2;   // stage-A table floats held in registers (at most)
-
-// A(z) for one sample (memoryless: c + W(|z|^2) z, W by Horner over NIA levels)
-__device__ __forceinline__ float2 cas_stage_a(const float (&T)[kCasTA], int NIA, float2 v)
-{
-    const float s = __builtin_fmaf(v.x, v.x, v.y * v.y);
-    float w00 = 0.f, w01 = 0.f, w10 = 0.f, w11 = 0.f, cr = 0.f, ci = 0.f;
-#pragma unroll
-    for (int j = kMaxNI - 1; j >= 0; --j) {
-        if (j < NIA) {
-            w00 = __builtin_fmaf(w00, s, T[4 * j + 0]);
-            w01 = __builtin_fmaf(w01, s, T[4 * j + 1]);
-            w10 = __builtin_fmaf(w10, s, T[4 * j + 2]);
-            w11 = __builtin_fmaf(w11, s, T[4 * j + 3]);
-        }
-        if (j == NIA) {
-            cr = T[4 * j];
-            ci = T[4 * j + 1];
-        }
-    }
-    if (NIA == kMaxNI) {
-        cr = T[4 * kMaxNI];
-        ci = T[4 * kMaxNI + 1];
-    }
-    return make_float2(__builtin_fmaf(w00, v.x, __builtin_fmaf(w01, v.y, cr)),
-                       __builtin_fmaf(w10, v.x, __builtin_fmaf(w11, v.y, ci)));
-}
-
 // Adjoint sum of one sample at input v from U_j = sum_k M_{j,k}^T g_{m+k}:
 // P + 2 Q v with P = sum_j s^j U_j, Q = sum_j j s^(j-1) (v . U_j), both by
 // Horner from the top level down.
@@ -172,11 +144,6 @@ __device__ __forceinline__ float2 cas_adjoint_sum(const float (&Ux)[NI], const f
     return make_float2(__builtin_fmaf(2.f * q, v.x, px), __builtin_fmaf(2.f * q, v.y, py));
 }
 
-__device__ __forceinline__ float2 cas_load(const float2 *__restrict__ r, int64_t m, int64_t n)
-{
-    return (m >= 0 && m < n) ? r[m] : make_float2(0.f, 0.f);
-}
-
 // Both tables into registers, once per thread.
 template <int NIB, int LB>
 __device__ __forceinline__ void cas_tables(const CasParams &p, float (&ta)[kCasTA], float (&tb)[4 * LB * NIB + 2])
@@ -186,23 +153,6 @@ __device__ __forceinline__ void cas_tables(const CasParams &p, float (&ta)[kCasT
 #pragma unroll
     for (int e = 0; e < 4 * LB * NIB + 2; ++e) tb[e] = p.B[e];
 }
-
-// This thread's quads: (row, quad) starting at q0 and advanced by the grid
-// stride without a division.
-struct CasWalk {
-    int64_t row, k, dr, dk;
-    __device__ CasWalk(int64_t q0, int64_t stride, int64_t qpr)
-        : row(q0 / qpr), k(q0 - (q0 / qpr) * qpr), dr(stride / qpr), dk(stride - (stride / qpr) * qpr) {}
-    __device__ void next(int64_t qpr)
-    {
-        row += dr;
-        k += dk;
-        if (k >= qpr) {
-            k -= qpr;
-            ++row;
-        }
-    }
-};
 
 // Forward: E partials and dE/dy.
 template <int NIB, int LB>
@@ -433,6 +383,12 @@ static dpd_status cas_check(const dpd_plan *A, const dpd_plan *B, const void *p0
     };
     if (lap(out, p0) || lap(out, p1)) return DPD_EINVAL;
     return DPD_OK;
+}
+
+hipError_t launch_loss_finalize(const float *partials, int nblk, double inv_n, float *loss, hipStream_t st)
+{
+    hipLaunchKernelGGL(loss_finalize, dim3(1), dim3(kBlock), 0, st, partials, nblk, inv_n, loss);
+    return hipGetLastError();
 }
 
 static int cas_grid(int64_t total)

@@ -76,6 +76,8 @@ _SIGS = {
     "dpd_cascade_loss_grad": [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, _vp, _vp, _vp,
                               ctypes.c_size_t],
     "dpd_cascade_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64],
+    "dpd_transmit_loss_grad": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, _vp, _vp, _vp,
+                               ctypes.c_size_t],
     "dpd_adam_step": [_vp, _vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float,
                       ctypes.c_float, ctypes.c_float],
     "dpd_ls_ws_size": [_vp, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
@@ -275,6 +277,13 @@ def dpd_cascade_loss_grad(plan_a, plan_b, stream, z_ptr, x_ptr, rows, n, ld, sca
 def dpd_cascade_backward(plan_a, plan_b, stream, z_ptr, gy_ptr, gz_ptr, rows, n, ld):
     _check(lib().dpd_cascade_backward(plan_a, plan_b, stream, z_ptr, gy_ptr, gz_ptr, int(rows), int(n), int(ld)),
            "dpd_cascade_backward")
+
+
+def dpd_transmit_loss_grad(plan_p, plan_a, plan_b, stream, coeffs_ptr, x_ptr, z_ptr, rows, n, ld, scale, loss_ptr,
+                           gy_ptr, ws_ptr, ws_bytes):
+    _check(lib().dpd_transmit_loss_grad(plan_p, plan_a, plan_b, stream, coeffs_ptr, x_ptr, z_ptr, int(rows), int(n),
+                                        int(ld), float(scale), loss_ptr, gy_ptr, ws_ptr, int(ws_bytes)),
+           "dpd_transmit_loss_grad")
 
 
 def dpd_adam_step(stream, p_ptr, g_ptr, m_ptr, v_ptr, count, step, lr, beta1=0.9, beta2=0.999,

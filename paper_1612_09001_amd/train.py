@@ -3,15 +3,18 @@
 ``FusedTrainer.step()`` runs one full-batch gradient step entirely in libdpd
 kernels, on buffers allocated once:
 
-  z = DPD(x)                 forward, coefficients read from the device
-  E, dE/dy                   the synthetic transmitter u = IQ(z), y = PA(u)
-                             (pa.py) fused with the loss E = mean |y/G - x|^2
-                             and its gradient (dpd_cascade_loss_grad: u and y
-                             are never stored)
+  z, E, dE/dy                the predistorter (coefficients read from the
+                             device), the synthetic transmitter u = IQ(z),
+                             y = PA(u) (pa.py) and the loss E = mean |y/G - x|^2
+                             with its gradient in one kernel
+                             (dpd_transmit_loss_grad: u and y are never
+                             stored, z is written once for the adjoint)
   dE/dz                      adjoint of PA and IQ (dpd_cascade_backward)
   dE/dcoeffs                 adjoint of the predistorter (coefficients only)
   Adam                       update of the K complex coefficients
 
+``one_pass=False`` runs the predistorter as its own launch before the fused
+transmitter (dpd_apply_coeffs, then dpd_cascade_loss_grad);
 ``fused_transmitter=False`` runs the transmitter and its adjoint as separate
 launches per stage (IQ, PA, loss; PA and IQ adjoints) instead.
 
@@ -31,7 +34,7 @@ from .pa import SyntheticPA, iq_coeffs, pa_coeffs
 
 class FusedTrainer:
     def __init__(self, x, main_orders, conj_orders, L, coeffs0, lr=1e-3, betas=(0.9, 0.999),
-                 eps=1e-8, fused_transmitter=True):
+                 eps=1e-8, fused_transmitter=True, one_pass=True):
         if x.dim() != 2 or not x.is_contiguous():
             raise ValueError("x must be a contiguous (rows, n) complex64 GPU tensor")
         self.x = x
@@ -42,6 +45,9 @@ class FusedTrainer:
         self.coeffs = torch.as_tensor(np.asarray(coeffs0, dtype=np.complex64)).to(dev).contiguous()
         self.pa = SyntheticPA()
         self.fused_transmitter = bool(fused_transmitter)
+        # predistorter, transmitter and loss in one kernel (dpd_transmit_loss_grad)
+        # where the stages are the ones it is built for
+        self.one_pass = bool(one_pass) and max(list(main_orders) + list(conj_orders)) <= 9 and L <= 8
         self.z = torch.empty_like(x)
         self.gy = torch.empty_like(x)
         self.gz = torch.empty_like(x)
@@ -66,13 +72,18 @@ class FusedTrainer:
         st = _dpd.current_stream()
         R, N, ld = self.rows, self.n, self.n
         P = lambda t: t.data_ptr()
-        _dpd.dpd_apply_coeffs(self.plan.handle, st, P(self.coeffs), P(self.x), P(self.z), R, N, ld)
         iq, pa = self.pa.iq.handle, self.pa.pa.handle
-        if self.fused_transmitter:
+        if self.fused_transmitter and self.one_pass:
+            _dpd.dpd_transmit_loss_grad(self.plan.handle, iq, pa, st, P(self.coeffs), P(self.x), P(self.z), R, N, ld,
+                                        1.0 / self.pa.gain, P(self.loss), P(self.gy), P(self.ws), self.ws_bytes)
+            _dpd.dpd_cascade_backward(iq, pa, st, P(self.z), P(self.gy), P(self.gz), R, N, ld)
+        elif self.fused_transmitter:
+            _dpd.dpd_apply_coeffs(self.plan.handle, st, P(self.coeffs), P(self.x), P(self.z), R, N, ld)
             _dpd.dpd_cascade_loss_grad(iq, pa, st, P(self.z), P(self.x), R, N, ld, 1.0 / self.pa.gain,
                                        P(self.loss), P(self.gy), P(self.ws), self.ws_bytes)
             _dpd.dpd_cascade_backward(iq, pa, st, P(self.z), P(self.gy), P(self.gz), R, N, ld)
         else:
+            _dpd.dpd_apply_coeffs(self.plan.handle, st, P(self.coeffs), P(self.x), P(self.z), R, N, ld)
             _dpd.dpd_apply_rows(iq, st, P(self.z), P(self.u), R, N, ld)
             _dpd.dpd_apply_rows(pa, st, P(self.u), P(self.y), R, N, ld)
             _dpd.dpd_loss_grad(st, P(self.y), P(self.x), R * N, 1.0 / self.pa.gain, P(self.loss),

@@ -154,3 +154,77 @@ def test_cascade_rejects_unsupported_stages(torch):
     with pytest.raises(dpd.DPDError):   # output overlapping an input
         dpd.dpd_cascade_backward(ok_a.handle, ok_a.handle, st, z.data_ptr(), out.data_ptr(), z.data_ptr(), 1, 64,
                                  64)
+
+
+# Rows of whole 512-sample chunks take the streaming form: one chunk per wave
+# (many_rows, one_chunk, three_chunks), and runs of two and three chunks per
+# wave over 999-chunk rows, so that runs start inside rows and cross them.
+@pytest.mark.parametrize("rows,n,ld,off", [(3, 5000, 5000, 0), (2, 4099, 4104, 0), (1, 1, 1, 0), (2, 777, 781, 1),
+                                           (64, 1 << 14, 1 << 14, 0), (1, 512, 512, 0), (1, 1536, 1540, 0),
+                                           (3, 512 * 999, 512 * 999, 0), (5, 512 * 999, 512 * 999, 0)],
+                         ids=["aligned", "ragged_rows", "one_sample", "unaligned_8B", "many_rows", "one_chunk",
+                              "three_chunks", "runs_cross_rows", "runs_of_three"])
+@pytest.mark.parametrize("dpd_shape", [([1, 3, 5, 7], [1, 3, 5, 7], 6), ([1, 3, 5], [1, 3], 4),
+                                       ([1, 3, 5, 7, 9], [1, 3, 5, 7, 9], 8)], ids=["P7_L6", "P5_L4", "P9_L8"])
+def test_transmit_loss_grad_one_pass(torch, orc, rows, n, ld, off, dpd_shape):
+    """Predistorter, transmitter and loss in one kernel: z and dE/dy bitwise
+    those of dpd_apply_coeffs followed by dpd_cascade_loss_grad, the loss within
+    FP32 summation-order rounding of theirs, and all three against the FP64
+    oracle applied stage by stage."""
+    from paper_1612_09001_amd import dpd
+
+    A, B = _stages("synthetic_pa")
+    mo, co, L = dpd_shape
+    h = signals.aph_coeffs(mo, co, L, config_id=73)
+    h[0] += 1.0
+    x = np.stack([signals.ofdm_16qam(n, config_id=74, stream_id=r) for r in range(rows)])
+    P = dpd.Plan(mo, co, L, np.zeros_like(h))      # the coefficients come from the device
+    pa_, pb_ = dpd.Plan(*A), dpd.Plan(*B)
+    base = torch.zeros(rows * ld + off + 2, dtype=torch.complex64, device="cuda")
+    xd = base[off:off + rows * ld].view(rows, ld) if rows * ld else base[:0].view(rows, ld)
+    xd[:, :n] = torch.from_numpy(x)
+    hd = torch.from_numpy(h).cuda()
+    outs = []
+    for one_pass in (True, False):
+        zb = torch.full((rows * ld + off + 2,), complex(5.0, 5.0), dtype=torch.complex64, device="cuda")
+        gb = torch.full_like(zb, complex(5.0, 5.0))
+        z = zb[off:off + rows * ld]
+        g = gb[off:off + rows * ld]
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        wsb = dpd.dpd_loss_ws_size(rows * n)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        st = dpd.current_stream()
+        if one_pass:
+            dpd.dpd_transmit_loss_grad(P.handle, pa_.handle, pb_.handle, st, hd.data_ptr(), xd.data_ptr(), z.data_ptr(),
+                                       rows, n, ld, 0.1, loss.data_ptr(), g.data_ptr(), ws.data_ptr(), wsb)
+        else:
+            dpd.dpd_apply_coeffs(P.handle, st, hd.data_ptr(), xd.data_ptr(), z.data_ptr(), rows, n, ld)
+            dpd.dpd_cascade_loss_grad(pa_.handle, pb_.handle, st, z.data_ptr(), xd.data_ptr(), rows, n, ld, 0.1,
+                                      loss.data_ptr(), g.data_ptr(), ws.data_ptr(), wsb)
+        torch.cuda.synchronize()
+        outs.append((z.view(rows, ld).cpu().numpy(), g.view(rows, ld).cpu().numpy(), float(loss.item())))
+    (z1, g1, e1), (z2, g2, e2) = outs
+    assert np.array_equal(z1[:, :n], z2[:, :n]) and np.array_equal(g1[:, :n], g2[:, :n])
+    assert np.all(z1[:, n:] == np.complex64(complex(5.0, 5.0)))      # nothing written past n
+    assert abs(e1 - e2) <= 1e-6 * e2
+    zr = np.stack([orc.forward(x[r], mo, co, L, h) for r in range(rows)])
+    E, gy = _oracle_loss(orc, zr, x, A, B, 0.1)
+    assert_parity(z1[:, :n].reshape(-1), zr.reshape(-1), "z")
+    assert_parity(g1[:, :n].reshape(-1), gy.reshape(-1), "dE/dy")
+    assert abs(e1 - E) <= 1e-5 * E
+
+
+def test_transmit_loss_grad_unsupported_stages(torch):
+    from paper_1612_09001_amd import dpd
+
+    A, B = _stages("general")
+    P = dpd.Plan([1, 3], [1], 2, signals.aph_coeffs([1, 3], [1], 2, config_id=75))
+    x = torch.zeros(64, dtype=torch.complex64, device="cuda")
+    z, g = torch.zeros_like(x), torch.zeros_like(x)
+    ws = torch.empty(dpd.dpd_loss_ws_size(64), dtype=torch.uint8, device="cuda")
+    pa_, pb_ = dpd.Plan(*A), dpd.Plan(*B)      # kept alive for the call
+    with pytest.raises(dpd.DPDError) as e:
+        dpd.dpd_transmit_loss_grad(P.handle, pa_.handle, pb_.handle, dpd.current_stream(), 0,
+                                   x.data_ptr(), z.data_ptr(), 1, 64, 64, 0.1, 0, g.data_ptr(), ws.data_ptr(),
+                                   ws.numel())
+    assert e.value.status == dpd.DPD_EUNSUPPORTED
