@@ -86,15 +86,30 @@ dpd_status dpd_create(const int32_t *main_orders, int32_t n_main,
                       const int32_t *conj_orders, int32_t n_conj, int32_t L,
                       const float *coeffs_host, dpd_plan **out);
 
-/* dpd_destroy -- waits for the device, then frees the plan.  NULL is a no-op. */
+/* dpd_destroy -- frees the plan.  Freeing device memory waits for the device
+ * (work on every stream that may still read the plan's table), so destroy
+ * plans outside latency-critical loops.  NULL is a no-op. */
 dpd_status dpd_destroy(dpd_plan *plan);
 
 /* dpd_num_coeffs -- K, the number of complex coefficients of the plan. */
 dpd_status dpd_num_coeffs(const dpd_plan *plan, int32_t *K);
 
 /* dpd_set_coeffs -- replace the coefficients from host memory (2K floats).
- * Synchronous: waits for the device before overwriting the table. */
+ * Not tied to a stream, so it waits for the device (every stream) before
+ * overwriting the table: each call enqueued before it uses the old
+ * coefficients, each call after it the new ones.  In loops use
+ * dpd_set_coeffs_async or dpd_set_coeffs_device.
+ *
+ * dpd_set_coeffs_async -- the same update ordered on `stream` (NULL: the null
+ * stream): work enqueued on that stream before it sees the old coefficients,
+ * work after it the new ones; work on other streams that uses the plan is
+ * the caller's to order (events).  The host copies the table into a pinned
+ * staging buffer of the plan (allocated on the first call) and waits only for
+ * the previous copy out of that buffer; coeffs_host may be reused on return.
+ * Calls on one plan from several host threads must be serialized by the
+ * caller. */
 dpd_status dpd_set_coeffs(dpd_plan *plan, const float *coeffs_host);
+dpd_status dpd_set_coeffs_async(dpd_plan *plan, const float *coeffs_host, void *stream);
 
 /* dpd_set_coeffs_device -- replace the coefficients from device memory
  * (K complex64), stream-ordered on `stream` with no host synchronization.
@@ -153,7 +168,9 @@ dpd_status dpd_apply_hist(dpd_plan *plan, void *stream, const void *in, void *ou
  * gradients follow the convention dE/dRe + j dE/dIm (the one PyTorch uses).
  *   coeffs_dev   K complex64 on the device, or NULL to use the plan's (device
  *                coefficients go through the plan's second table, as in
- *                dpd_apply_coeffs; the plan's own coefficients are untouched)
+ *                dpd_apply_coeffs; the plan's own coefficients are untouched;
+ *                read only when grad_x is requested: dE/dcoeffs does not
+ *                depend on the coefficients)
  *   x            inputs of the forward call, rows x n with row stride ld
  *   grad_z       dE/dz for the outputs, same shape
  *   grad_x       receives dE/dx (same shape), or NULL to skip it
@@ -204,7 +221,9 @@ typedef struct dpd_stream_desc {
  * shorter), list them most expensive class first, upload the list (32 bytes
  * per chunk), and size the persistent grid.
  * `tune` may be NULL for the default launch shape.  The descriptor pointers
- * must stay valid for the life of the batch.  Synchronous. */
+ * must stay valid for the life of the batch.  Synchronous on the host (the
+ * chunk list and zeroed tables are in device memory on return; no device-wide
+ * wait). */
 dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_streams, const dpd_tune *tune,
                             dpd_batch **out);
 
@@ -221,7 +240,8 @@ dpd_status dpd_batch_apply_each(dpd_batch *batch, void *stream);
  * launch and its number of blocks. */
 dpd_status dpd_batch_info(const dpd_batch *batch, int64_t *n_tiles, int32_t *n_blocks);
 
-/* dpd_batch_destroy -- waits for the device, then frees the batch. */
+/* dpd_batch_destroy -- frees the batch; freeing device memory waits for the
+ * device, so kernels still reading the batch finish first. */
 dpd_status dpd_batch_destroy(dpd_batch *batch);
 
 /* --------------------------------------------------------------- training --

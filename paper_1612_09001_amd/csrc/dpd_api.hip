@@ -388,11 +388,15 @@ DPD_EXPORT dpd_status dpd_create(const int32_t *main_orders, int32_t n_main, con
     return DPD_OK;
 }
 
+// hipFree and hipHostFree wait for the device themselves: the plan's memory
+// is released only after every kernel that may read it has finished.
 DPD_EXPORT dpd_status dpd_destroy(dpd_plan *plan)
 {
     if (plan == nullptr) return DPD_OK;
-    hipError_t e = hipDeviceSynchronize();
-    if (plan->d_table) (void)hipFree(plan->d_table);
+    hipError_t e = hipSuccess;
+    if (plan->d_table) e = hipFree(plan->d_table);
+    if (plan->staged) (void)hipEventDestroy(plan->staged);
+    if (plan->h_stage) (void)hipHostFree(plan->h_stage);
     delete plan;
     return e == hipSuccess ? DPD_OK : hip_fail(e);
 }
@@ -412,6 +416,40 @@ DPD_EXPORT dpd_status dpd_set_coeffs(dpd_plan *plan, const float *coeffs_host)
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e);
     e = hipMemcpy(plan->d_table, M.data(), M.size() * sizeof(float), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+    plan->raw.assign(coeffs_host, coeffs_host + 2 * plan->K);
+    return DPD_OK;
+}
+
+// Stream-ordered: the precombined table goes through a pinned staging buffer
+// of the plan; before refilling it, the host waits only for the previous copy
+// out of it (the plan's event), not for the device.
+DPD_EXPORT dpd_status dpd_set_coeffs_async(dpd_plan *plan, const float *coeffs_host, void *stream)
+{
+    if (plan == nullptr || coeffs_host == nullptr) return DPD_EINVAL;
+    std::vector<float> M;
+    precombine_host(plan->map, coeffs_host, M);
+    const size_t bytes = M.size() * sizeof(float);
+    hipError_t e = hipSuccess;
+    if (plan->h_stage == nullptr) {
+        e = hipHostMalloc((void **)&plan->h_stage, bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            plan->h_stage = nullptr;
+            return e == hipErrorOutOfMemory ? DPD_ENOMEM : hip_fail(e);
+        }
+        e = hipEventCreateWithFlags(&plan->staged, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            plan->staged = nullptr;
+            return hip_fail(e);
+        }
+    } else {
+        e = hipEventSynchronize(plan->staged);
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    std::memcpy(plan->h_stage, M.data(), bytes);
+    const hipStream_t st = (hipStream_t)stream;
+    e = hipMemcpyAsync(plan->d_table, plan->h_stage, bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipEventRecord(plan->staged, st);
     if (e != hipSuccess) return hip_fail(e);
     plan->raw.assign(coeffs_host, coeffs_host + 2 * plan->K);
     return DPD_OK;

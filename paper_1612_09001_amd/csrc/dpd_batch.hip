@@ -259,8 +259,13 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
     b->grid = (int)std::min<int64_t>(cap, (b->n_full + waves - 1) / waves);
     b->tail_grid = (int)std::min<int64_t>(cap, (b->n_chunks - b->n_full + waves - 1) / waves);
     hipError_t e = hipGetDevice(&b->device);
+    // zero fills as synchronous host copies: complete on return, so no
+    // stream (whatever its flags) can see the buffers before they hold zeros
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_idle, (size_t)C * sizeof(float2));
-    if (e == hipSuccess) e = hipMemset(b->d_idle, 0, (size_t)C * sizeof(float2));
+    if (e == hipSuccess) {
+        const std::vector<float2> zeros((size_t)C, make_float2(0.f, 0.f));
+        e = hipMemcpy(b->d_idle, zeros.data(), zeros.size() * sizeof(float2), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) {
         BatchChunk idle;
         idle.in = b->d_idle;
@@ -275,9 +280,7 @@ DPD_EXPORT dpd_status dpd_batch_create(const dpd_stream_desc *desc, int32_t n_st
     if (e == hipSuccess) e = upload(&b->d_jobs, jobs);
     b->n_jobs = (int32_t)jobs.size();
     // + 4 floats: the idle entry reads table floats 0..3
-    if (e == hipSuccess) e = hipMalloc((void **)&b->d_tables, (size_t)(tab_total + 4) * sizeof(float));
-    if (e == hipSuccess) e = hipMemset(b->d_tables, 0, (size_t)(tab_total + 4) * sizeof(float));
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = upload(&b->d_tables, std::vector<float>((size_t)(tab_total + 4), 0.f));
     if (e != hipSuccess) {
         free_batch(b);
         return e == hipErrorOutOfMemory ? DPD_ENOMEM : hip_fail(e);
@@ -329,10 +332,11 @@ DPD_EXPORT dpd_status dpd_batch_info(const dpd_batch *b, int64_t *n_tiles, int32
     return DPD_OK;
 }
 
+// hipFree waits for the device itself, so in-flight batch kernels finish
+// before their chunk list and tables are released.
 DPD_EXPORT dpd_status dpd_batch_destroy(dpd_batch *b)
 {
     if (b == nullptr) return DPD_OK;
-    hipError_t e = hipDeviceSynchronize();
     free_batch(b);
-    return e == hipSuccess ? DPD_OK : hip_fail(e);
+    return DPD_OK;
 }

@@ -236,8 +236,10 @@ static dpd_status backward_impl(dpd_plan *plan, void *stream, const void *coeffs
         };
         if (ov(grad_x, x) || ov(grad_x, grad_z)) return DPD_EINVAL;
     }
+    // only dx reads the coefficients: dE/dcoeffs is the correlation of grad_z
+    // with the basis of x alone
     const float *table = plan->d_table;
-    if (coeffs_dev != nullptr) {
+    if (coeffs_dev != nullptr && want_dx) {
         hipError_t e = launch_prep(map, coeffs_dev, plan->d_table_call, st);
         if (e != hipSuccess) return hip_fail(e);
         table = plan->d_table_call;

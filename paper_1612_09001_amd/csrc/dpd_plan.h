@@ -17,6 +17,8 @@ struct dpd_plan {
     float *d_table = nullptr;    // precombined table (device)
     float *d_table_call = nullptr;  // table of the calls that pass device coefficients
                                     // (same allocation as d_table, right after it)
+    float *h_stage = nullptr;    // pinned staging of dpd_set_coeffs_async (created on first use)
+    hipEvent_t staged = nullptr; // recorded after the last copy out of h_stage
     int8_t ls_slot[32] = {};     // least squares: LDS row slot of each basis entry,
     std::once_flag ls_once;      // chosen on the first least-squares call
 };

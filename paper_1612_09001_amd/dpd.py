@@ -54,6 +54,7 @@ _SIGS = {
     "dpd_destroy": [_vp],
     "dpd_num_coeffs": [_vp, _i32p],
     "dpd_set_coeffs": [_vp, _f32p],
+    "dpd_set_coeffs_async": [_vp, _f32p, _vp],
     "dpd_set_coeffs_device": [_vp, _vp, _vp],
     "dpd_set_coeffs_device_if": [_vp, _vp, _vp, _vp],
     "dpd_set_tune": [_vp, ctypes.POINTER(dpd_tune)],
@@ -172,6 +173,13 @@ def dpd_set_coeffs(plan: int, coeffs_host):
     if f.size != 2 * dpd_num_coeffs(plan):
         raise ValueError("coefficient count does not match the plan")
     _check(lib().dpd_set_coeffs(plan, f.ctypes.data_as(_f32p)), "dpd_set_coeffs")
+
+
+def dpd_set_coeffs_async(plan: int, coeffs_host, stream: int):
+    f = _coeff_floats(coeffs_host)
+    if f.size != 2 * dpd_num_coeffs(plan):
+        raise ValueError("coefficient count does not match the plan")
+    _check(lib().dpd_set_coeffs_async(plan, f.ctypes.data_as(_f32p), stream), "dpd_set_coeffs_async")
 
 
 def dpd_set_coeffs_device(plan: int, coeffs_dev_ptr: int, stream: int):
@@ -381,13 +389,18 @@ class Plan:
         except Exception:
             pass
 
-    def set_coeffs(self, coeffs):
+    def set_coeffs(self, coeffs, ordered=False):
+        """Device coefficients: stream-ordered on torch's current stream.  Host
+        coefficients: the device-wide update, or with ordered=True the update
+        ordered on the current stream (dpd_set_coeffs_async)."""
         torch = _torch()
         if isinstance(coeffs, torch.Tensor) and coeffs.is_cuda:
             c = _dev_c64(coeffs, "coeffs").contiguous()
             if c.numel() != self.K:
                 raise ValueError("expected %d coefficients" % self.K)
             dpd_set_coeffs_device(self.handle, c.data_ptr(), current_stream())
+        elif ordered:
+            dpd_set_coeffs_async(self.handle, coeffs, current_stream())
         else:
             dpd_set_coeffs(self.handle, coeffs)
 

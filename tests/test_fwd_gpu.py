@@ -311,3 +311,27 @@ def test_graph_replay(torch, dpd, orc):
         assert np.array_equal(_host(z2), ze2), "replay %d apply_hist" % r
         prev = xs[r - 1][-(L - 1):] if r > 0 else np.zeros(L - 1, np.complex64)
         assert_parity(_host(z2), orc.forward(xs[r], mo, co, L, h, hist=prev), "replay %d" % r)
+
+
+def test_set_coeffs_async_is_stream_ordered(torch, dpd, orc):
+    """Host coefficients ordered on the stream: three applies with updates in
+    between, no host synchronization, each apply filtering with the
+    coefficients set before it (the second update refills the staging buffer
+    while the first copy may still be queued behind a long apply)."""
+    mo, co, L = [1, 3, 5], [1, 3], 4
+    hs = [signals.aph_coeffs(mo, co, L, config_id=c) for c in (131, 132, 133)]
+    x = signals.ofdm_16qam(1 << 22, config_id=131)
+    xd = _dev(torch, x)
+    plan = dpd.Plan(mo, co, L, hs[0])
+    outs = [plan.apply(xd)]
+    for h in hs[1:]:
+        plan.set_coeffs(h, ordered=True)
+        outs.append(plan.apply(xd))
+    torch.cuda.synchronize()
+    for i, (z, h) in enumerate(zip(outs, hs)):
+        zr = orc.forward(x[:1 << 16], mo, co, L, h)
+        assert_parity(_host(z)[:1 << 16], zr, "apply %d" % i)
+    # the async update leaves the same table bits as the device-wide one
+    plan2 = dpd.Plan(mo, co, L, hs[0])
+    plan2.set_coeffs(hs[2])
+    assert np.array_equal(_host(plan2.apply(xd)), _host(outs[2]))
