@@ -309,6 +309,30 @@ dpd_status dpd_transmit_loss_grad(dpd_plan *P, const dpd_plan *A, const dpd_plan
                                   int64_t ld, float scale, float *loss_dev, void *grad_y, void *ws,
                                   size_t ws_bytes);
 
+/* dpd_transmit_backward -- the backward pass of the learning step: dE/dz
+ * through the adjoint of the cascade (B at u = A(z), then A, as
+ * dpd_cascade_backward computes it) and from it the predistorter's coefficient
+ * gradient, dE/dcoeffs of Eq. (1) for the inputs x (as dpd_backward with
+ * grad_x NULL computes it; the coefficients of P are not read).  In one
+ * kernel when A is memoryless with order 1 in each branch, B has orders
+ * {1, 3, 5} and 3 taps, P orders up to 9 and up to 8 taps, n is a multiple of
+ * 256 and x, z, grad_y (and grad_z) are 16-byte aligned with an even row
+ * stride: dE/dz then stays on chip.  Otherwise the two passes run with dE/dz
+ * in grad_z, which must then be given (DPD_EUNSUPPORTED if it is NULL).
+ *   x, z, grad_y  device complex64, rows x n at stride ld: the predistorter's
+ *                 input and output and dE/dy (dpd_transmit_loss_grad writes z
+ *                 and grad_y)
+ *   grad_z        device, same layout, receives dE/dz, or NULL; must not
+ *                 overlap x, z or grad_y
+ *   grad_coeffs   device, receives the K complex64 gradients (required)
+ *   ws, ws_bytes  device workspace of at least dpd_backward_ws_size(P) bytes
+ * Deterministic (fixed-order reductions, FP64 finalisation).  Allocates
+ * nothing. */
+dpd_status dpd_transmit_backward(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream,
+                                 const void *x, const void *z, const void *grad_y, void *grad_z,
+                                 void *grad_coeffs, int64_t rows, int64_t n, int64_t ld, void *ws,
+                                 size_t ws_bytes);
+
 /* ------------------------------------------------------- least squares --
  * The paper's coefficient estimate (section 2.2, Eq. 2): with the plan's
  * basis, row m of Psi is

@@ -37,6 +37,7 @@ UNITS += [("dpd_batch_inst.hip", ["-DDPD_BATCH_S=%d" % s], "dpd_batch_s%d.o" % s
 UNITS += [("dpd_batch.hip", [], "dpd_batch.o")]
 UNITS += [("dpd_train.hip", [], "dpd_train.o")]
 UNITS += [("dpd_transmit.hip", [], "dpd_transmit.o")]
+UNITS += [("dpd_transmit_bwd.hip", [], "dpd_transmit_bwd.o")]
 UNITS += [("dpd_ls.hip", [], "dpd_ls.o")]
 
 

@@ -201,6 +201,14 @@ size_t bwd_ws_bytes(const CoefMap &map)
     return (size_t)(blocks * E * (int64_t)sizeof(float) + 256);
 }
 
+hipError_t launch_bwd_finalize(const float *partials, int nblk, const CoefMap &map, float2 *grad_coeffs,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(bwd_finalize, dim3((uint32_t)(map.L * map.NI + 1)), dim3(kBlock), 0, st, partials, nblk,
+                       map, grad_coeffs);
+    return hipGetLastError();
+}
+
 }  // namespace dpd
 
 using namespace dpd;

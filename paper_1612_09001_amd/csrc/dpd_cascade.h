@@ -1,5 +1,5 @@
 // Pieces of the transmitter-cascade kernels shared by the training
-// translation units (dpd_train.hip, dpd_transmit.hip).
+// translation units (dpd_train.hip, dpd_transmit.hip, dpd_transmit_bwd.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -38,6 +38,62 @@ __device__ __forceinline__ float2 cas_stage_a(const float (&T)[kCasTA], int NIA,
                        __builtin_fmaf(w10, v.x, __builtin_fmaf(w11, v.y, ci)));
 }
 
+// P + 2 Q v of the adjoint of a map at v from its U_j (levels j < NI):
+// P = sum_j s^j U_j and Q = sum_j j s^(j-1) v.U_j by Horner, s = |v|^2.
+template <int NI>
+__device__ __forceinline__ float2 cas_adjoint_sum(const float (&Ux)[NI], const float (&Uy)[NI], float2 v)
+{
+    const float s = __builtin_fmaf(v.x, v.x, v.y * v.y);
+    float px = Ux[NI - 1], py = Uy[NI - 1], q = 0.f;
+#pragma unroll
+    for (int j = NI - 1; j >= 1; --j) {
+        q = __builtin_fmaf(q, s, (float)j * __builtin_fmaf(v.x, Ux[j], v.y * Uy[j]));
+        px = __builtin_fmaf(px, s, Ux[j - 1]);
+        py = __builtin_fmaf(py, s, Uy[j - 1]);
+    }
+    return make_float2(__builtin_fmaf(2.f * q, v.x, px), __builtin_fmaf(2.f * q, v.y, py));
+}
+
+// Adjoint of stage B (NIB levels, LB taps, table tb) at u_m = uv:
+// U_j = sum_k M_{j,k}^T g_{m+k} from g[0..LB-1] = dE/dy at m .. m + LB - 1.
+template <int NIB, int LB>
+__device__ __forceinline__ float2 cas_b_adjoint(const float *tb, const float2 *g, float2 uv)
+{
+    float Ux[NIB], Uy[NIB];
+#pragma unroll
+    for (int j = 0; j < NIB; ++j) {
+        float ax = 0.f, ay = 0.f;
+#pragma unroll
+        for (int k = 0; k < LB; ++k) {
+            const float *t = tb + 4 * (k * NIB + j);
+            ax = __builtin_fmaf(t[0], g[k].x, __builtin_fmaf(t[2], g[k].y, ax));
+            ay = __builtin_fmaf(t[1], g[k].x, __builtin_fmaf(t[3], g[k].y, ay));
+        }
+        Ux[j] = ax;
+        Uy[j] = ay;
+    }
+    return cas_adjoint_sum<NIB>(Ux, Uy, uv);
+}
+
+// Adjoint of the memoryless stage A (one tap, NIA levels) at z from gu:
+// V_j = M_j^T gu, then the same P + 2 Q z by Horner from the top level down.
+__device__ __forceinline__ float2 cas_a_adjoint(const float (&ta)[kCasTA], int NIA, float2 z1, float2 gu)
+{
+    const float sa = __builtin_fmaf(z1.x, z1.x, z1.y * z1.y);
+    float px = 0.f, py = 0.f, qa = 0.f;
+#pragma unroll
+    for (int j = kMaxNI - 1; j >= 0; --j) {
+        if (j < NIA) {
+            const float vx = __builtin_fmaf(ta[4 * j + 0], gu.x, ta[4 * j + 2] * gu.y);
+            const float vy = __builtin_fmaf(ta[4 * j + 1], gu.x, ta[4 * j + 3] * gu.y);
+            px = __builtin_fmaf(px, sa, vx);
+            py = __builtin_fmaf(py, sa, vy);
+            if (j >= 1) qa = __builtin_fmaf(qa, sa, (float)j * __builtin_fmaf(z1.x, vx, z1.y * vy));
+        }
+    }
+    return make_float2(__builtin_fmaf(2.f * qa, z1.x, px), __builtin_fmaf(2.f * qa, z1.y, py));
+}
+
 __device__ __forceinline__ float2 cas_load(const float2 *__restrict__ r, int64_t m, int64_t n)
 {
     return (m >= 0 && m < n) ? r[m] : make_float2(0.f, 0.f);
@@ -62,5 +118,12 @@ struct CasWalk {
 
 // FP64 sum of loss partials into *loss (one block; dpd_train.hip).
 hipError_t launch_loss_finalize(const float *partials, int nblk, double inv_n, float *loss, hipStream_t st);
+
+// Coefficient-gradient partials of the predistorter's backward (dpd_bwd.hip):
+// the workspace bytes one call needs, and the FP64 finalisation of nblk
+// per-block partials into K complex gradients.
+size_t bwd_ws_bytes(const CoefMap &map);
+hipError_t launch_bwd_finalize(const float *partials, int nblk, const CoefMap &map, float2 *grad_coeffs,
+                               hipStream_t st);
 
 }  // namespace dpd

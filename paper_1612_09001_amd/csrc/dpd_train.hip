@@ -127,22 +127,6 @@ struct CasParams {
     int vec;                 // rows start 16-byte aligned: whole quads use 16-byte accesses
 };
 
-// Adjoint sum of one sample at input v from U_j = sum_k M_{j,k}^T g_{m+k}:
-// P + 2 Q v with P = sum_j s^j U_j, Q = sum_j j s^(j-1) (v . U_j), both by
-// Horner from the top level down.
-template <int NI>
-__device__ __forceinline__ float2 cas_adjoint_sum(const float (&Ux)[NI], const float (&Uy)[NI], float2 v)
-{
-    const float s = __builtin_fmaf(v.x, v.x, v.y * v.y);
-    float px = Ux[NI - 1], py = Uy[NI - 1], q = 0.f;
-#pragma unroll
-    for (int j = NI - 1; j >= 1; --j) {
-        q = __builtin_fmaf(q, s, (float)j * __builtin_fmaf(v.x, Ux[j], v.y * Uy[j]));
-        px = __builtin_fmaf(px, s, Ux[j - 1]);
-        py = __builtin_fmaf(py, s, Uy[j - 1]);
-    }
-    return make_float2(__builtin_fmaf(2.f * q, v.x, px), __builtin_fmaf(2.f * q, v.y, py));
-}
 
 // Both tables into registers, once per thread.
 template <int NIB, int LB>
@@ -292,37 +276,8 @@ __global__ void __launch_bounds__(kBlock) cascade_bwd_kernel(CasParams p)
 #pragma unroll
         for (int i = 0; i < kCasQ; ++i) {
             const float2 uv = cas_stage_a(ta, p.NIA, zv[i]);
-            // adjoint of B at u_m: U_j = sum_k M_{j,k}^T g_{m+k}
-            float Ux[NIB], Uy[NIB];
-#pragma unroll
-            for (int j = 0; j < NIB; ++j) {
-                float ax = 0.f, ay = 0.f;
-#pragma unroll
-                for (int k = 0; k < LB; ++k) {
-                    const float *t = tb + 4 * (k * NIB + j);
-                    ax = __builtin_fmaf(t[0], g[i + k].x, __builtin_fmaf(t[2], g[i + k].y, ax));
-                    ay = __builtin_fmaf(t[1], g[i + k].x, __builtin_fmaf(t[3], g[i + k].y, ay));
-                }
-                Ux[j] = ax;
-                Uy[j] = ay;
-            }
-            const float2 gu = cas_adjoint_sum<NIB>(Ux, Uy, uv);
-            // adjoint of A at z_m (one tap, NIA levels): V_j = M_j^T gu, the
-            // same P + 2 Q v by Horner from the top level down
-            const float2 z1 = zv[i];
-            const float sa = __builtin_fmaf(z1.x, z1.x, z1.y * z1.y);
-            float px = 0.f, py = 0.f, qa = 0.f;
-#pragma unroll
-            for (int j = kMaxNI - 1; j >= 0; --j) {
-                if (j < p.NIA) {
-                    const float vx = __builtin_fmaf(ta[4 * j + 0], gu.x, ta[4 * j + 2] * gu.y);
-                    const float vy = __builtin_fmaf(ta[4 * j + 1], gu.x, ta[4 * j + 3] * gu.y);
-                    px = __builtin_fmaf(px, sa, vx);
-                    py = __builtin_fmaf(py, sa, vy);
-                    if (j >= 1) qa = __builtin_fmaf(qa, sa, (float)j * __builtin_fmaf(z1.x, vx, z1.y * vy));
-                }
-            }
-            res[i] = make_float2(__builtin_fmaf(2.f * qa, z1.x, px), __builtin_fmaf(2.f * qa, z1.y, py));
+            const float2 gu = cas_b_adjoint<NIB, LB>(tb, g + i, uv);
+            res[i] = cas_a_adjoint(ta, p.NIA, zv[i], gu);
         }
         if (vec) {
             reinterpret_cast<float4 *>(out + m0)[0] = make_float4(res[0].x, res[0].y, res[1].x, res[1].y);

@@ -1,0 +1,378 @@
+// The backward pass of the coefficient-learning step in one kernel: the
+// adjoint of the two-stage transmitter model (stage B, the PA with memory, at
+// u = A(z); then the memoryless stage A at z) gives dE/dz, and the coefficient
+// gradient of the predistorter (Eq. 1 / Algorithm 1 differentiated in its
+// coefficients) correlates dE/dz with the basis of x at once:
+//     dE/dM_{j,k}[r][c] = sum_m G_{m+k}[r] (s_m^j v_m)[c],   G = dE/dz,
+// with v_m = (Re x_m, Im x_m), s_m = |x_m|^2 -- so dE/dz never goes to memory.
+// The predistorter's coefficients are not read (the gradient does not depend
+// on them).
+//
+// Rows of whole 256-sample chunks, 16-byte aligned.  Each wave takes a
+// contiguous run of chunks of the flattened rows and walks it from its end:
+// lane l owns samples 4l .. 4l + 3 of a chunk, computes G there from z and
+// dE/dy (dE/dy staged with the LB - 1 samples after the chunk), and pairs G at
+// m .. m + L - 1 with the basis at m, so the L - 1 values of G after the chunk
+// are the first ones of the chunk handled just before (carried in registers),
+// zero past the row end, and -- for the first chunk of a run inside a row --
+// evaluated directly by L - 1 lanes.  The per-sample arithmetic of G is that
+// of dpd_cascade_backward (bitwise the same values).  The coefficient-gradient
+// accumulation, its fixed-order reduction to one FP32 partial per block and
+// the FP64 finalisation are those of dpd_backward.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+
+#include "dpd.h"
+#include "dpd_bwd_kernels.h"
+#include "dpd_cascade.h"
+#include "dpd_plan.h"
+
+#define DPD_EXPORT extern "C" __attribute__((visibility("default")))
+
+namespace dpd {
+
+constexpr int kTbNIB = 3, kTbLB = 3;   // stage B of the one-pass form: orders {1,3,5}, 3 taps
+constexpr int kTbMaxNI = 5;            // predistorter: orders up to 9
+constexpr int kTbMaxL = kSpecL;        // predistorter: up to 8 taps
+constexpr int kTbChunk = 64 * kBwdS;   // samples per wave chunk
+
+struct TbParams {
+    const float *A, *B;       // transmitter stage tables
+    const float2 *x, *z, *gy; // rows x n at stride ld
+    float2 *gz;               // dE/dz out (nullptr: not written)
+    float *partials;          // [gridDim.x][4 L NI + 2]
+    int64_t rows, n, ld, tpr; // tpr = n / chunk
+};
+
+template <int NI, int L>
+__global__ void __launch_bounds__(kBlock) transmit_bwd_kernel(TbParams p)
+{
+    constexpr int NIB = kTbNIB, LB = kTbLB;
+    constexpr int S = kBwdS, C = kTbChunk, NV = S / 2, WAVES = kBlock / 64;
+    constexpr int W = S + L - 1;        // G window of a lane
+    constexpr int HG = L - 1;           // G after the chunk
+    constexpr int HY = LB - 1;          // dE/dy after the chunk
+    constexpr int E = 4 * L * NI + 2;
+    constexpr int GSLOTS = C + HG + (C + HG) / S + 1;
+    constexpr int YSLOTS = C + HY + (C + HY) / S + 1;
+    constexpr int XSLOTS = C + C / S;
+    __shared__ __align__(16) float2 gs[WAVES][GSLOTS];
+    __shared__ __align__(16) float2 ys[WAVES][YSLOTS];
+    __shared__ __align__(16) float2 xsh[WAVES][XSLOTS];
+    __shared__ __align__(16) float2 zsh[WAVES][XSLOTS];
+    __shared__ float red[WAVES * E];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    float ta[kCasTA], tb[4 * LB * NIB + 2];
+#pragma unroll
+    for (int e = 0; e < kCasTA; ++e) ta[e] = e < 6 ? p.A[e] : 0.f;
+#pragma unroll
+    for (int e = 0; e < 4 * LB * NIB + 2; ++e) tb[e] = p.B[e];
+    float2 *G = gs[wv];
+    float2 *Y = ys[wv];
+    float2 *X = xsh[wv];
+    float2 *Z = zsh[wv];
+    auto slot = [](int d) { return d + d / S; };
+
+    float acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = 0.f;
+
+    // G at sample m of a row from z and dE/dy (zero past the row end): the
+    // arithmetic of dpd_cascade_backward
+    auto g_at = [&](const float2 *zr, const float2 *yr, int64_t m) {
+        const float2 zv = cas_load(zr, m, p.n);
+        float2 g[LB];
+#pragma unroll
+        for (int k = 0; k < LB; ++k) g[k] = cas_load(yr, m + k, p.n);
+        const float2 uv = cas_stage_a(ta, 1, zv);
+        const float2 gu = cas_b_adjoint<NIB, LB>(tb, g, uv);
+        return cas_a_adjoint(ta, 1, zv, gu);
+    };
+
+    struct Regs {
+        float4 z[NV], y[NV], x[NV];
+        float2 yh;   // dE/dy at t0 + C + lane (lanes < HY; zero past the row end)
+    };
+    auto load = [&](Regs &R, int64_t row, int64_t t0) {
+        const int64_t base = row * p.ld + t0;
+        const v4f *z4 = reinterpret_cast<const v4f *>(p.z + base);
+        const v4f *y4 = reinterpret_cast<const v4f *>(p.gy + base);
+        const v4f *x4 = reinterpret_cast<const v4f *>(p.x + base);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const v4f a = __builtin_nontemporal_load(z4 + lane + 64 * i);
+            R.z[i] = make_float4(a.x, a.y, a.z, a.w);
+        }
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const v4f a = __builtin_nontemporal_load(y4 + lane + 64 * i);
+            R.y[i] = make_float4(a.x, a.y, a.z, a.w);
+        }
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const v4f a = __builtin_nontemporal_load(x4 + lane + 64 * i);
+            R.x[i] = make_float4(a.x, a.y, a.z, a.w);
+        }
+        // the LB - 1 values after the chunk: inside the row unless it is the row's last chunk
+        const int hl = lane < HY ? lane : HY - 1;
+        const bool in = t0 + C < p.n;
+        const float2 v = p.gy[row * p.ld + (in ? t0 + C + hl : t0)];
+        R.yh = in ? v : make_float2(0.f, 0.f);
+    };
+    auto stage = [&](const Regs &R) {
+        wave_lds_order();   // the previous chunk's LDS reads are done
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int j = 2 * (lane + 64 * i);
+            Z[slot(j)] = make_float2(R.z[i].x, R.z[i].y);
+            Z[slot(j) + 1] = make_float2(R.z[i].z, R.z[i].w);
+            Y[slot(j)] = make_float2(R.y[i].x, R.y[i].y);
+            Y[slot(j) + 1] = make_float2(R.y[i].z, R.y[i].w);
+            X[slot(j)] = make_float2(R.x[i].x, R.x[i].y);
+            X[slot(j) + 1] = make_float2(R.x[i].z, R.x[i].w);
+        }
+        if (lane < HY) Y[slot(C + lane)] = R.yh;
+        wave_lds_order();
+    };
+    // one staged chunk; `carry` holds G at t0 + C + lane (lanes < HG) and
+    // leaves with G at t0 + lane, the values the chunk before needs
+    auto compute = [&](int64_t row, int64_t t0, float2 &carry) {
+        float2 gz[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const float2 zv = Z[slot(lane * S + i)];
+            float2 g[LB];
+#pragma unroll
+            for (int k = 0; k < LB; ++k) g[k] = Y[slot(lane * S + i + k)];
+            const float2 uv = cas_stage_a(ta, 1, zv);
+            const float2 gu = cas_b_adjoint<NIB, LB>(tb, g, uv);
+            gz[i] = cas_a_adjoint(ta, 1, zv, gu);
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) G[slot(lane * S + i)] = gz[i];
+        if (HG > 0 && lane < HG) G[slot(C + lane)] = carry;
+        wave_lds_order();
+        if (HG > 0) {
+            const float2 c = G[slot(lane < HG ? lane : 0)];
+            carry = lane < HG ? c : make_float2(0.f, 0.f);
+        }
+        float ga[W], gb[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const float2 g = G[slot(lane * S + w)];
+            ga[w] = g.x;
+            gb[w] = g.y;
+        }
+        float va[S], vb[S], sq[S], pw[S];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const float2 v = X[slot(lane * S + i)];
+            va[i] = v.x;
+            vb[i] = v.y;
+            sq[i] = __builtin_fmaf(v.x, v.x, v.y * v.y);
+            pw[i] = 1.f;
+        }
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+            float ba[S], bb[S];
+#pragma unroll
+            for (int i = 0; i < S; ++i) {
+                ba[i] = pw[i] * va[i];
+                bb[i] = pw[i] * vb[i];
+            }
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+#pragma unroll
+                for (int i = 0; i < S; ++i) {
+                    const float a = ga[i + k], b = gb[i + k];
+                    float *u = &acc[4 * (k * NI + j)];
+                    u[0] = __builtin_fmaf(a, ba[i], u[0]);
+                    u[1] = __builtin_fmaf(a, bb[i], u[1]);
+                    u[2] = __builtin_fmaf(b, ba[i], u[2]);
+                    u[3] = __builtin_fmaf(b, bb[i], u[3]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < S; ++i) pw[i] *= sq[i];
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            acc[E - 2] += ga[i];
+            acc[E - 1] += gb[i];
+        }
+        if (p.gz != nullptr) {
+            // G back through LDS so every store instruction writes 1 KiB
+            v4f *o4 = reinterpret_cast<v4f *>(p.gz + row * p.ld + t0);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int j = 2 * (lane + 64 * i);
+                const float2 u = G[slot(j)], w = G[slot(j) + 1];
+                const v4f v = {u.x, u.y, w.x, w.y};
+                __builtin_nontemporal_store(v, o4 + lane + 64 * i);
+            }
+        }
+    };
+
+    const int64_t total = p.rows * p.tpr;
+    const int64_t nw = (int64_t)gridDim.x * WAVES;
+    const int64_t gw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * WAVES + wv;
+    const int64_t per = (total + nw - 1) / nw;
+    const int64_t c_begin = gw * per < total ? gw * per : total;
+    const int64_t c_end = c_begin + per < total ? c_begin + per : total;
+    if (c_begin < c_end) {
+        // the run's last chunk first
+        int64_t row = (c_end - 1) / p.tpr;
+        int64_t k = (c_end - 1) - row * p.tpr;
+        float2 carry = make_float2(0.f, 0.f);
+        if (HG > 0) {
+            // G after the chunk: zero past the row end, else evaluated here
+            const int64_t m = (k + 1) * C + (lane < HG ? lane : 0);
+            const float2 v = g_at(p.z + row * p.ld, p.gy + row * p.ld, m);
+            carry = lane < HG ? v : make_float2(0.f, 0.f);
+        }
+        Regs R;
+        load(R, row, k * C);
+        stage(R);
+        for (int64_t left = c_end - c_begin; left > 1; --left) {
+            const int64_t crow = row, ck = k;
+            if (k == 0) {
+                --row;
+                k = p.tpr - 1;
+            } else {
+                --k;
+            }
+            load(R, row, k * C);
+            compute(crow, ck * C, carry);
+            if (ck == 0) carry = make_float2(0.f, 0.f);   // the chunk before ends a row
+            stage(R);
+        }
+        compute(row, k * C, carry);
+    }
+
+    // wave -> block -> one FP32 partial per block, fixed order
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const float t = wave_sum(acc[e]);
+        if (lane == 0) red[wv * E + e] = t;
+    }
+    __syncthreads();
+    for (int e = tid; e < E; e += kBlock) {
+        float t = 0.f;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) t += red[w * E + e];
+        p.partials[(int64_t)blockIdx.x * E + e] = t;
+    }
+}
+
+typedef void (*TbKernel)(TbParams);
+
+template <int NI, int L>
+struct TbEntry {
+    static void fill(TbKernel (&f)[kTbMaxNI][kTbMaxL])
+    {
+        f[NI - 1][L - 1] = &transmit_bwd_kernel<NI, L>;
+        if constexpr (L < kTbMaxL)
+            TbEntry<NI, L + 1>::fill(f);
+        else if constexpr (NI < kTbMaxNI)
+            TbEntry<NI + 1, 1>::fill(f);
+    }
+};
+
+struct TbTable {
+    TbKernel k[kTbMaxNI][kTbMaxL];
+    TbTable() { TbEntry<1, 1>::fill(k); }
+};
+
+static const TbTable &tb_table()
+{
+    static const TbTable t;
+    return t;
+}
+
+int num_cus();
+
+static int tb_occupancy(int NI, int L)
+{
+    static std::atomic<int> cache[kTbMaxNI][kTbMaxL] = {};
+    int v = cache[NI - 1][L - 1].load(std::memory_order_relaxed);
+    if (v == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, (const void *)tb_table().k[NI - 1][L - 1], kBlock, 0) !=
+                hipSuccess ||
+            v < 1)
+            v = 1;
+        cache[NI - 1][L - 1].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+}  // namespace dpd
+
+using namespace dpd;
+
+DPD_EXPORT dpd_status dpd_transmit_backward(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream,
+                                            const void *x, const void *z, const void *grad_y, void *grad_z,
+                                            void *grad_coeffs, int64_t rows, int64_t n, int64_t ld, void *ws,
+                                            size_t ws_bytes)
+{
+    if (P == nullptr || A == nullptr || B == nullptr || grad_coeffs == nullptr) return DPD_EINVAL;
+    if (A->map.L != 1) return DPD_EINVAL;
+    if (rows < 0 || n < 0 || (rows > 1 && ld < n)) return DPD_EINVAL;
+    if (ws == nullptr || ws_bytes < bwd_ws_bytes(P->map) || (uintptr_t)ws % 4 != 0) return DPD_EINVAL;
+    if ((uintptr_t)grad_coeffs % 8 != 0) return DPD_EINVAL;
+    const int64_t N = rows * n;
+    const int64_t rs = rows > 1 ? ld : n;
+    if (N > 0) {
+        if (x == nullptr || z == nullptr || grad_y == nullptr) return DPD_EINVAL;
+        for (const void *q : {x, z, grad_y, (const void *)grad_z})
+            if ((uintptr_t)q % 8 != 0) return DPD_EINVAL;
+        if (grad_z != nullptr) {
+            const size_t span = (size_t)(((rows - 1) * rs + n) * (int64_t)sizeof(float2));
+            const auto lap = [&](const void *a, const void *b) {
+                const uintptr_t u = (uintptr_t)a, v = (uintptr_t)b;
+                return u < v + span && v < u + span;
+            };
+            if (lap(grad_z, x) || lap(grad_z, z) || lap(grad_z, grad_y)) return DPD_EINVAL;
+        }
+    }
+    const bool stages_ok = A->map.NI == 1 && B->map.NI == kTbNIB && B->map.L == kTbLB &&
+                           P->map.NI <= kTbMaxNI && P->map.L <= kTbMaxL;
+    const bool aligned = (uintptr_t)x % 16 == 0 && (uintptr_t)z % 16 == 0 && (uintptr_t)grad_y % 16 == 0 &&
+                         (uintptr_t)grad_z % 16 == 0 && rs % 2 == 0;
+    const hipStream_t hs = (hipStream_t)stream;
+    if (!(stages_ok && aligned && n % kTbChunk == 0)) {
+        // other shapes: the two passes, dE/dz through the caller's grad_z
+        if (N > 0 && grad_z == nullptr) return DPD_EUNSUPPORTED;
+        dpd_status st = dpd_cascade_backward(A, B, stream, z, grad_y, grad_z, rows, n, ld);
+        if (st != DPD_OK) return st;
+        return dpd_backward(const_cast<dpd_plan *>(P), stream, nullptr, x, grad_z, nullptr, grad_coeffs, rows, n,
+                            ld, ws, ws_bytes);
+    }
+    int nblk = 0;
+    if (N > 0) {
+        TbParams p;
+        p.A = A->d_table;
+        p.B = B->d_table;
+        p.x = (const float2 *)x;
+        p.z = (const float2 *)z;
+        p.gy = (const float2 *)grad_y;
+        p.gz = (float2 *)grad_z;
+        p.partials = (float *)ws;
+        p.rows = rows;
+        p.n = n;
+        p.ld = rs;
+        p.tpr = n / kTbChunk;
+        // one round of resident blocks, at most two per CU, each wave a run of chunks
+        const int NI = P->map.NI, L = P->map.L;
+        const int64_t cap = (int64_t)num_cus() * std::min(tb_occupancy(NI, L), 2);
+        nblk = (int)std::max<int64_t>(1, std::min<int64_t>(cap, (rows * p.tpr + 3) / 4));
+        hipLaunchKernelGGL(tb_table().k[NI - 1][L - 1], dim3(nblk), dim3(kBlock), 0, hs, p);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e);
+    }
+    hipError_t e = launch_bwd_finalize((const float *)ws, nblk, P->map, (float2 *)grad_coeffs, hs);
+    return e == hipSuccess ? DPD_OK : hip_fail(e);
+}

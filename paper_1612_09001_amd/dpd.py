@@ -79,6 +79,7 @@ _SIGS = {
     "dpd_cascade_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64],
     "dpd_transmit_loss_grad": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, _vp, _vp, _vp,
                                ctypes.c_size_t],
+    "dpd_transmit_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, ctypes.c_size_t],
     "dpd_adam_step": [_vp, _vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float,
                       ctypes.c_float, ctypes.c_float],
     "dpd_ls_ws_size": [_vp, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
@@ -292,6 +293,13 @@ def dpd_transmit_loss_grad(plan_p, plan_a, plan_b, stream, coeffs_ptr, x_ptr, z_
     _check(lib().dpd_transmit_loss_grad(plan_p, plan_a, plan_b, stream, coeffs_ptr, x_ptr, z_ptr, int(rows), int(n),
                                         int(ld), float(scale), loss_ptr, gy_ptr, ws_ptr, int(ws_bytes)),
            "dpd_transmit_loss_grad")
+
+
+def dpd_transmit_backward(plan_p, plan_a, plan_b, stream, x_ptr, z_ptr, gy_ptr, gz_ptr, gc_ptr, rows, n, ld,
+                          ws_ptr, ws_bytes):
+    _check(lib().dpd_transmit_backward(plan_p, plan_a, plan_b, stream, x_ptr, z_ptr, gy_ptr, gz_ptr, gc_ptr,
+                                       int(rows), int(n), int(ld), ws_ptr, int(ws_bytes)),
+           "dpd_transmit_backward")
 
 
 def dpd_adam_step(stream, p_ptr, g_ptr, m_ptr, v_ptr, count, step, lr, beta1=0.9, beta2=0.999,

@@ -74,9 +74,13 @@ class FusedTrainer:
         P = lambda t: t.data_ptr()
         iq, pa = self.pa.iq.handle, self.pa.pa.handle
         if self.fused_transmitter and self.one_pass:
+            # forward in one pass, backward in another: dE/dz stays on chip where
+            # the shapes allow (else dpd_transmit_backward goes through self.gz)
             _dpd.dpd_transmit_loss_grad(self.plan.handle, iq, pa, st, P(self.coeffs), P(self.x), P(self.z), R, N, ld,
                                         1.0 / self.pa.gain, P(self.loss), P(self.gy), P(self.ws), self.ws_bytes)
-            _dpd.dpd_cascade_backward(iq, pa, st, P(self.z), P(self.gy), P(self.gz), R, N, ld)
+            gz = 0 if N % 256 == 0 else P(self.gz)
+            _dpd.dpd_transmit_backward(self.plan.handle, iq, pa, st, P(self.x), P(self.z), P(self.gy), gz,
+                                       P(self.gc), R, N, ld, P(self.ws), self.ws_bytes)
         elif self.fused_transmitter:
             _dpd.dpd_apply_coeffs(self.plan.handle, st, P(self.coeffs), P(self.x), P(self.z), R, N, ld)
             _dpd.dpd_cascade_loss_grad(iq, pa, st, P(self.z), P(self.x), R, N, ld, 1.0 / self.pa.gain,
@@ -92,8 +96,9 @@ class FusedTrainer:
                               P(self.ws), self.ws_bytes)
             _dpd.dpd_backward(iq, st, 0, P(self.z), P(self.gu), P(self.gz), 0, R, N, ld,
                               P(self.ws), self.ws_bytes)
-        _dpd.dpd_backward(self.plan.handle, st, P(self.coeffs), P(self.x), P(self.gz), 0, P(self.gc),
-                          R, N, ld, P(self.ws), self.ws_bytes)
+        if not (self.fused_transmitter and self.one_pass):
+            _dpd.dpd_backward(self.plan.handle, st, P(self.coeffs), P(self.x), P(self.gz), 0, P(self.gc),
+                              R, N, ld, P(self.ws), self.ws_bytes)
         self.t += 1
         _dpd.dpd_adam_step(st, P(self.coeffs), P(self.gc), P(self.m), P(self.v), 2 * self.K, self.t,
                            self.lr, self.betas[0], self.betas[1], self.eps)

@@ -4,7 +4,7 @@ oracle applied stage by stage."""
 import numpy as np
 import pytest
 
-from metrics import assert_parity
+from metrics import assert_dcoef, assert_parity
 from paper_1612_09001_amd import signals
 
 pytestmark = pytest.mark.gpu
@@ -228,3 +228,96 @@ def test_transmit_loss_grad_unsupported_stages(torch):
                                    x.data_ptr(), z.data_ptr(), 1, 64, 64, 0.1, 0, g.data_ptr(), ws.data_ptr(),
                                    ws.numel())
     assert e.value.status == dpd.DPD_EUNSUPPORTED
+
+
+# Rows of whole 256-sample chunks take the one-pass kernel (one chunk per wave;
+# runs of two and three chunks over 999-chunk rows, starting inside rows and
+# crossing them); the others the two passes through grad_z.
+@pytest.mark.parametrize("rows,n,ld,off", [(3, 5120, 5120, 0), (64, 1 << 14, 1 << 14, 0), (1, 256, 256, 0),
+                                           (2, 1280, 1284, 0), (3, 256 * 999, 256 * 999, 0),
+                                           (5, 256 * 999, 256 * 999, 0), (2, 4099, 4104, 0), (2, 777, 781, 1),
+                                           (1, 1, 1, 0)],
+                         ids=["aligned", "many_rows", "one_chunk", "padded_rows", "runs_cross_rows", "runs_of_three",
+                              "ragged_rows", "unaligned_8B", "one_sample"])
+@pytest.mark.parametrize("dpd_shape", [([1, 3, 5, 7], [1, 3, 5, 7], 6), ([1, 3, 5], [1, 3], 4),
+                                       ([1, 3, 5, 7, 9], [1, 3, 5, 7, 9], 8), ([1, 3], [1], 1)],
+                         ids=["P7_L6", "P5_L4", "P9_L8", "P3_L1"])
+def test_transmit_backward_one_pass(torch, orc, rows, n, ld, off, dpd_shape):
+    """Cascade adjoint and coefficient gradient in one kernel: dE/dz (when
+    asked for) bitwise that of dpd_cascade_backward, the gradient with and
+    without dE/dz written bitwise equal, and every gradient entry against the
+    FP64 oracle's coefficient gradient for the same dE/dz."""
+    from paper_1612_09001_amd import dpd
+
+    A, B = _stages("synthetic_pa")
+    mo, co, L = dpd_shape
+    h = signals.aph_coeffs(mo, co, L, config_id=76)
+    x = np.stack([signals.ofdm_16qam(n, config_id=77, stream_id=r) for r in range(rows)])
+    z = np.stack([signals.ofdm_16qam(n, config_id=78, stream_id=r) for r in range(rows)])
+    gy = np.stack([signals.ofdm_16qam(n, config_id=79, stream_id=r) for r in range(rows)]) * 1e-3
+    P = dpd.Plan(mo, co, L, h)
+    pa_, pb_ = dpd.Plan(*A), dpd.Plan(*B)
+
+    def dev(a):
+        b = torch.zeros(rows * ld + off + 2, dtype=torch.complex64, device="cuda")
+        v = b[off:off + rows * ld]
+        v.view(rows, ld)[:, :n] = torch.from_numpy(a.astype(np.complex64))
+        return b, v
+
+    (xb, xd), (zb, zd), (yb, yd) = dev(x), dev(z), dev(gy)
+    gzb = torch.full((rows * ld + off + 2,), complex(5.0, 5.0), dtype=torch.complex64, device="cuda")
+    gzd = gzb[off:off + rows * ld]
+    ref_b = torch.full_like(gzb, complex(5.0, 5.0))
+    ref_d = ref_b[off:off + rows * ld]
+    wsb = dpd.dpd_backward_ws_size(P.handle, rows, n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    st = dpd.current_stream()
+    one_pass = n % 256 == 0 and off == 0 and ld % 2 == 0
+    gcs = []
+    for want_gz in (True, False):
+        gc = torch.zeros(P.K, dtype=torch.complex64, device="cuda")
+        if not want_gz and not one_pass:
+            with pytest.raises(dpd.DPDError) as e:
+                dpd.dpd_transmit_backward(P.handle, pa_.handle, pb_.handle, st, xd.data_ptr(), zd.data_ptr(),
+                                          yd.data_ptr(), 0, gc.data_ptr(), rows, n, ld, ws.data_ptr(), wsb)
+            assert e.value.status == dpd.DPD_EUNSUPPORTED
+            continue
+        dpd.dpd_transmit_backward(P.handle, pa_.handle, pb_.handle, st, xd.data_ptr(), zd.data_ptr(), yd.data_ptr(),
+                                  gzd.data_ptr() if want_gz else 0, gc.data_ptr(), rows, n, ld, ws.data_ptr(), wsb)
+        torch.cuda.synchronize()
+        gcs.append(gc.cpu().numpy())
+    dpd.dpd_cascade_backward(pa_.handle, pb_.handle, st, zd.data_ptr(), yd.data_ptr(), ref_d.data_ptr(), rows, n, ld)
+    torch.cuda.synchronize()
+    g1 = gzd.view(rows, ld).cpu().numpy()
+    g2 = ref_d.view(rows, ld).cpu().numpy()
+    assert np.array_equal(g1[:, :n], g2[:, :n]), "dE/dz differs from dpd_cascade_backward"
+    assert np.all(g1[:, n:] == np.complex64(complex(5.0, 5.0))) and np.all(
+        gzb.cpu().numpy()[:off] == np.complex64(complex(5.0, 5.0)))
+    if len(gcs) == 2:
+        assert np.array_equal(gcs[0], gcs[1])
+    ref = sum(orc.backward(x[r], mo, co, L, h, g2[r, :n].astype(np.complex128), want_dx=False)[1]
+              for r in range(rows))
+    assert_dcoef(gcs[0], ref, "transmit backward %s" % (dpd_shape,))
+
+
+def test_transmit_backward_bad_arguments(torch):
+    from paper_1612_09001_amd import dpd
+
+    A, B = _stages("synthetic_pa")
+    P = dpd.Plan([1, 3], [1], 2, signals.aph_coeffs([1, 3], [1], 2, config_id=80))
+    pa_, pb_ = dpd.Plan(*A), dpd.Plan(*B)
+    x = torch.zeros(512, dtype=torch.complex64, device="cuda")
+    z, gy, gz = torch.zeros_like(x), torch.zeros_like(x), torch.zeros_like(x)
+    gc = torch.zeros(P.K, dtype=torch.complex64, device="cuda")
+    wsb = dpd.dpd_backward_ws_size(P.handle, 1, 512)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    st = dpd.current_stream()
+    call = lambda **k: dpd.dpd_transmit_backward(
+        P.handle, k.get("a", pa_.handle), pb_.handle, st, x.data_ptr(), z.data_ptr(), k.get("gy", gy.data_ptr()),
+        k.get("gz", gz.data_ptr()), k.get("gc", gc.data_ptr()), 1, 512, 512, ws.data_ptr(), k.get("wsb", wsb))
+    call()
+    for kw in ({"gc": 0}, {"wsb": wsb - 4}, {"gz": z.data_ptr()}, {"gz": gy.data_ptr()}, {"a": pb_.handle}):
+        with pytest.raises(dpd.DPDError) as e:
+            call(**kw)
+        assert e.value.status == dpd.DPD_EINVAL, kw
+    torch.cuda.synchronize()
