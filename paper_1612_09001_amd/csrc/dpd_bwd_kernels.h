@@ -60,6 +60,44 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+// One DPP step of a lane reduction: x from the lane that CTRL selects (rows
+// outside RMASK read zero).
+template <int CTRL, int RMASK>
+__device__ __forceinline__ float dpp_from(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, RMASK, 0xf, false));
+}
+
+// Sum over the 64 lanes, complete in lane 63 (the other lanes hold partial
+// sums), by DPP row operations -- no LDS round trips: quad sums (quad_perm
+// 1,0,3,2 and 2,3,0,1), 8- and 16-lane sums (row_half_mirror, row_mirror),
+// then rows 1 and 3 add rows 0 and 2 (row_bcast:15) and rows 2 and 3 add the
+// sum of rows 0..1 (row_bcast:31).  Fixed order: the same inputs give the
+// same bits.
+__device__ __forceinline__ float wave_sum_to_lane63(float v)
+{
+    v += dpp_from<0xB1, 0xf>(v);
+    v += dpp_from<0x4E, 0xf>(v);
+    v += dpp_from<0x141, 0xf>(v);
+    v += dpp_from<0x140, 0xf>(v);
+    v += dpp_from<0x142, 0xa>(v);
+    v += dpp_from<0x143, 0xc>(v);
+    return v;
+}
+
+// The wave totals of E per-lane accumulators into out[0..E) (LDS): every
+// accumulator reduced in place, then lane 63 stores them all.
+template <int E>
+__device__ __forceinline__ void store_wave_totals(float (&acc)[E], float *out, int lane)
+{
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = wave_sum_to_lane63(acc[e]);
+    if (lane == 63) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) out[e] = acc[e];
+    }
+}
+
 template <bool B>
 struct BwdTag {
     static constexpr bool value = B;
@@ -329,11 +367,7 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
 
     if constexpr (DC) {
         // wave -> block -> one FP32 partial per block, fixed order
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const float t = wave_sum(acc[e]);
-            if (lane == 0) red[wv * E + e] = t;
-        }
+        store_wave_totals<E>(acc, red + wv * E, lane);
         __syncthreads();
         for (int e = tid; e < E; e += kBlock) {
             float t = 0.f;

@@ -12,28 +12,35 @@ constexpr int kLossBlocks = 1024;   // loss partials (one per block of the loss 
 
 constexpr int kCasTA = 4 * kMaxNI + 2;   // stage-A table floats held in registers (at most)
 
-// A(z) for one sample (memoryless: c + W(|z|^2) z, W by Horner over NIA levels)
+// A(z) for one sample (memoryless: c + W(|z|^2) z, W by Horner over NIA
+// levels from the top one down)
 __device__ __forceinline__ float2 cas_stage_a(const float (&T)[kCasTA], int NIA, float2 v)
 {
-    const float s = __builtin_fmaf(v.x, v.x, v.y * v.y);
-    float w00 = 0.f, w01 = 0.f, w10 = 0.f, w11 = 0.f, cr = 0.f, ci = 0.f;
+    float w00 = T[0], w01 = T[1], w10 = T[2], w11 = T[3];
+    if (NIA > 1) {
+        const float s = __builtin_fmaf(v.x, v.x, v.y * v.y);
 #pragma unroll
-    for (int j = kMaxNI - 1; j >= 0; --j) {
-        if (j < NIA) {
-            w00 = __builtin_fmaf(w00, s, T[4 * j + 0]);
-            w01 = __builtin_fmaf(w01, s, T[4 * j + 1]);
-            w10 = __builtin_fmaf(w10, s, T[4 * j + 2]);
-            w11 = __builtin_fmaf(w11, s, T[4 * j + 3]);
+        for (int j = kMaxNI - 1; j >= 0; --j) {
+            if (j == NIA - 1) {
+                w00 = T[4 * j + 0];
+                w01 = T[4 * j + 1];
+                w10 = T[4 * j + 2];
+                w11 = T[4 * j + 3];
+            } else if (j < NIA - 1) {
+                w00 = __builtin_fmaf(w00, s, T[4 * j + 0]);
+                w01 = __builtin_fmaf(w01, s, T[4 * j + 1]);
+                w10 = __builtin_fmaf(w10, s, T[4 * j + 2]);
+                w11 = __builtin_fmaf(w11, s, T[4 * j + 3]);
+            }
         }
+    }
+    float cr = T[4 * kMaxNI], ci = T[4 * kMaxNI + 1];
+#pragma unroll
+    for (int j = kMaxNI - 1; j >= 1; --j)
         if (j == NIA) {
             cr = T[4 * j];
             ci = T[4 * j + 1];
         }
-    }
-    if (NIA == kMaxNI) {
-        cr = T[4 * kMaxNI];
-        ci = T[4 * kMaxNI + 1];
-    }
     return make_float2(__builtin_fmaf(w00, v.x, __builtin_fmaf(w01, v.y, cr)),
                        __builtin_fmaf(w10, v.x, __builtin_fmaf(w11, v.y, ci)));
 }
@@ -43,15 +50,22 @@ __device__ __forceinline__ float2 cas_stage_a(const float (&T)[kCasTA], int NIA,
 template <int NI>
 __device__ __forceinline__ float2 cas_adjoint_sum(const float (&Ux)[NI], const float (&Uy)[NI], float2 v)
 {
-    const float s = __builtin_fmaf(v.x, v.x, v.y * v.y);
-    float px = Ux[NI - 1], py = Uy[NI - 1], q = 0.f;
+    if constexpr (NI == 1) {
+        return make_float2(Ux[0], Uy[0]);
+    } else {
+        const float s = __builtin_fmaf(v.x, v.x, v.y * v.y);
+        float px = Ux[NI - 1], py = Uy[NI - 1];
+        float q = (float)(NI - 1) * __builtin_fmaf(v.x, Ux[NI - 1], v.y * Uy[NI - 1]);
+        px = __builtin_fmaf(px, s, Ux[NI - 2]);
+        py = __builtin_fmaf(py, s, Uy[NI - 2]);
 #pragma unroll
-    for (int j = NI - 1; j >= 1; --j) {
-        q = __builtin_fmaf(q, s, (float)j * __builtin_fmaf(v.x, Ux[j], v.y * Uy[j]));
-        px = __builtin_fmaf(px, s, Ux[j - 1]);
-        py = __builtin_fmaf(py, s, Uy[j - 1]);
+        for (int j = NI - 2; j >= 1; --j) {
+            q = __builtin_fmaf(q, s, (float)j * __builtin_fmaf(v.x, Ux[j], v.y * Uy[j]));
+            px = __builtin_fmaf(px, s, Ux[j - 1]);
+            py = __builtin_fmaf(py, s, Uy[j - 1]);
+        }
+        return make_float2(__builtin_fmaf(2.f * q, v.x, px), __builtin_fmaf(2.f * q, v.y, py));
     }
-    return make_float2(__builtin_fmaf(2.f * q, v.x, px), __builtin_fmaf(2.f * q, v.y, py));
 }
 
 // Adjoint of stage B (NIB levels, LB taps, table tb) at u_m = uv:
@@ -76,21 +90,34 @@ __device__ __forceinline__ float2 cas_b_adjoint(const float *tb, const float2 *g
 }
 
 // Adjoint of the memoryless stage A (one tap, NIA levels) at z from gu:
-// V_j = M_j^T gu, then the same P + 2 Q z by Horner from the top level down.
+// V_j = M_j^T gu, then P + 2 Q z by Horner from the top level down (one level:
+// the transpose alone).
 __device__ __forceinline__ float2 cas_a_adjoint(const float (&ta)[kCasTA], int NIA, float2 z1, float2 gu)
 {
+    const float v0x = __builtin_fmaf(ta[0], gu.x, ta[2] * gu.y);
+    const float v0y = __builtin_fmaf(ta[1], gu.x, ta[3] * gu.y);
+    if (NIA == 1) return make_float2(v0x, v0y);
     const float sa = __builtin_fmaf(z1.x, z1.x, z1.y * z1.y);
     float px = 0.f, py = 0.f, qa = 0.f;
 #pragma unroll
-    for (int j = kMaxNI - 1; j >= 0; --j) {
+    for (int j = kMaxNI - 1; j >= 1; --j) {
         if (j < NIA) {
             const float vx = __builtin_fmaf(ta[4 * j + 0], gu.x, ta[4 * j + 2] * gu.y);
             const float vy = __builtin_fmaf(ta[4 * j + 1], gu.x, ta[4 * j + 3] * gu.y);
-            px = __builtin_fmaf(px, sa, vx);
-            py = __builtin_fmaf(py, sa, vy);
-            if (j >= 1) qa = __builtin_fmaf(qa, sa, (float)j * __builtin_fmaf(z1.x, vx, z1.y * vy));
+            const float d = (float)j * __builtin_fmaf(z1.x, vx, z1.y * vy);
+            if (j == NIA - 1) {
+                px = vx;
+                py = vy;
+                qa = d;
+            } else {
+                px = __builtin_fmaf(px, sa, vx);
+                py = __builtin_fmaf(py, sa, vy);
+                qa = __builtin_fmaf(qa, sa, d);
+            }
         }
     }
+    px = __builtin_fmaf(px, sa, v0x);
+    py = __builtin_fmaf(py, sa, v0y);
     return make_float2(__builtin_fmaf(2.f * qa, z1.x, px), __builtin_fmaf(2.f * qa, z1.y, py));
 }
 

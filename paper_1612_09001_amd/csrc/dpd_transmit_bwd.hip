@@ -254,11 +254,7 @@ __global__ void __launch_bounds__(kBlock) transmit_bwd_kernel(TbParams p)
     }
 
     // wave -> block -> one FP32 partial per block, fixed order
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const float t = wave_sum(acc[e]);
-        if (lane == 0) red[wv * E + e] = t;
-    }
+    store_wave_totals<E>(acc, red + wv * E, lane);
     __syncthreads();
     for (int e = tid; e < E; e += kBlock) {
         float t = 0.f;

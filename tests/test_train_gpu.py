@@ -30,11 +30,15 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-def test_fused_gradient_matches_fp64_chain(torch, orc):
+# n = 5000: both passes of the step in their general forms; 5120: the forward
+# general, the backward in one pass (whole 256-sample chunks); 8192: both in
+# their one-pass streaming forms.
+@pytest.mark.parametrize("n", [5000, 5120, 8192])
+def test_fused_gradient_matches_fp64_chain(torch, orc, n):
     import oracle.pa as opa
     from paper_1612_09001_amd.train import FusedTrainer
 
-    x, xd = _data(torch, 3, 5000)
+    x, xd = _data(torch, 3, n)
     h = signals.aph_coeffs(*ORDERS, L, config_id=50)       # away from the optimum
     tr = FusedTrainer(xd, *ORDERS, L, h, lr=0.0)
     loss = tr.step()
@@ -43,6 +47,26 @@ def test_fused_gradient_matches_fp64_chain(torch, orc):
     assert abs(float(loss.item()) - E) <= 1e-5 * E
     # three FP32 stages (predistorter, modulator, PA), each within 1e-5
     assert_dcoef(tr.gc.cpu().numpy(), g, "chain gradient", entry_max=1e-4, rel_max=1e-4)
+
+
+def test_one_pass_kernels_match_separate_ones(torch):
+    """The step with the one-pass forward and backward kernels against the
+    same step from the separate library calls: equal losses to FP32 summation
+    order over 30 Adam steps, equal coefficient gradients at the start."""
+    from paper_1612_09001_amd.train import FusedTrainer
+
+    _, xd = _data(torch, 4, 8192, cid=6)
+    h0 = signals.identity_coeffs(*ORDERS, L)
+    a = FusedTrainer(xd, *ORDERS, L, h0, one_pass=True)
+    b = FusedTrainer(xd, *ORDERS, L, h0, one_pass=False)
+    la, lb = [], []
+    for i in range(30):
+        la.append(float(a.step().item()))
+        lb.append(float(b.step().item()))
+        if i == 0:
+            assert_dcoef(a.gc.cpu().numpy(), b.gc.cpu().numpy(), "one pass vs separate", entry_max=1e-5,
+                         rel_max=1e-6)
+    assert np.all(np.abs(np.array(la) - np.array(lb)) <= 1e-5 * np.array(lb)), (la[-1], lb[-1])
 
 
 def test_three_paths_agree(torch):
