@@ -725,6 +725,25 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
            "at_rms_0.25_lr_1e-3": {"guard_band_distortion_db_no_dpd": guard(h0, xd, x[0]),
                                    "guard_band_distortion_db_learned": guard(h_fused, xd, x[0])}}
     del tr2, x2d
+    # the same on two non-contiguous carriers: distortion in the gap between them
+    x3 = np.stack([signals.two_carrier(n, config_id=3, stream_id=r, rms=0.2) for r in range(rows)])
+    x3d = torch.from_numpy(x3).cuda()
+    tr3 = FusedTrainer(x3d, orders, orders, L, h0, lr=0.03)
+    for _ in range(steps):
+        tr3.step()
+    h3 = tr3.coeffs.cpu().numpy()
+
+    def gap(hh):
+        pl = dpd.Plan(orders, orders, L, hh)
+        _, yy = spa.forward(pl.apply(x3d[0].contiguous()))
+        return round(spectral.distortion_regrowth_db(yy.cpu().numpy() / spa.gain, x3[0], bands=spectral.TWO_CARRIER), 2)
+
+    _, y64 = oila.transmit(orc, x3[0], (orders, orders), L, h3)
+    sup["two_carrier_gap_distortion_db_no_dpd"] = gap(h0)
+    sup["two_carrier_gap_distortion_db_learned"] = gap(h3)
+    sup["two_carrier_gap_distortion_db_learned_fp64_chain"] = round(
+        spectral.distortion_regrowth_db(y64[0] / oila.GAIN, x3[0], bands=spectral.TWO_CARRIER), 2)
+    del tr3, x3d
     return {"workload": "64x2^18 OFDM-like, DPD {1,3,5,7} main+conj L=6, synthetic PA, Adam 1e-3",
             "accuracy_step0": acc, "suppression": sup,
             "grad_step_ms_fused": round(med(fused_ms), 4),

@@ -113,8 +113,9 @@ struct BwdTag {
 // filtered, so the compiler's counter waits never cover the prefetch.  Each
 // lane owns S consecutive samples m and reads G_{m..m+S+L-2}.  One pass over
 // the power levels j (ascending) produces both gradients: U_j by taps for dx
-// (P = sum s^j U_j and Q = sum j s^(j-1) v.U_j accumulated with explicit
-// powers), and G (x) s^j v into the per-lane coefficient accumulators.
+// (P = sum s^j U_j and 2Q = sum 2j s^(j-1) v.U_j accumulated with explicit
+// powers; dx = P + 2Q v), and G (x) s^j v into the per-lane coefficient
+// accumulators.
 template <int NI, int L, bool DX, bool DC>
 __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
 {
@@ -228,7 +229,7 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
         for (int i = 0; i < S; ++i) {
             Pa[i] = Pb[i] = Q[i] = 0.f;
             pw[i] = 1.f;     // s^j
-            pwl[i] = 0.f;    // j s^(j-1)
+            pwl[i] = 0.f;    // 2 j s^(j-1)
         }
 #pragma unroll
         for (int j = 0; j < NI; ++j) {
@@ -263,13 +264,14 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
 #pragma unroll
             for (int i = 0; i < S; ++i) {
                 if constexpr (DX) {
-                    Pa[i] = __builtin_fmaf(pw[i], Ua[i], Pa[i]);
-                    Pb[i] = __builtin_fmaf(pw[i], Ub[i], Pb[i]);
+                    // level 0 has s^0 = 1: P starts at U_0
+                    Pa[i] = j == 0 ? Ua[i] : __builtin_fmaf(pw[i], Ua[i], Pa[i]);
+                    Pb[i] = j == 0 ? Ub[i] : __builtin_fmaf(pw[i], Ub[i], Pb[i]);
                     if (j > 0) {
                         const float d = __builtin_fmaf(va[i], Ua[i], vb[i] * Ub[i]);
-                        Q[i] = __builtin_fmaf(pwl[i], d, Q[i]);
+                        Q[i] = j == 1 ? pwl[i] * d : __builtin_fmaf(pwl[i], d, Q[i]);
                     }
-                    pwl[i] = (float)(j + 1) * pw[i];
+                    pwl[i] = (float)(2 * (j + 1)) * pw[i];   // 2 (j + 1) s^j: Q carries the factor 2 of dx
                 }
                 pw[i] *= sq[i];
             }
@@ -301,9 +303,8 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
             float dxa[S], dxb[S];
 #pragma unroll
             for (int i = 0; i < S; ++i) {
-                const float q2 = 2.f * Q[i];
-                dxa[i] = __builtin_fmaf(q2, va[i], Pa[i]);
-                dxb[i] = __builtin_fmaf(q2, vb[i], Pb[i]);
+                dxa[i] = __builtin_fmaf(Q[i], va[i], Pa[i]);
+                dxb[i] = __builtin_fmaf(Q[i], vb[i], Pb[i]);
             }
             float2 *gxr = p.gx + row * p.ld;
             if constexpr (FULL) {
