@@ -333,6 +333,33 @@ dpd_status dpd_transmit_backward(const dpd_plan *P, const dpd_plan *A, const dpd
                                  void *grad_coeffs, int64_t rows, int64_t n, int64_t ld, void *ws,
                                  size_t ws_bytes);
 
+/* dpd_learn_step -- one whole coefficient-learning step in one call (four
+ * launches): the one-pass forward of dpd_transmit_loss_grad with the
+ * coefficients coeffs_dev, the one-pass backward of dpd_transmit_backward,
+ * then one launch that finalises the loss and the gradient (FP64, as those
+ * calls do) and applies the Adam update of dpd_adam_step to coeffs_dev in
+ * place.  Results are bitwise those of the three calls followed by
+ * dpd_adam_step.  Arguments as there:
+ *   coeffs_dev       K complex64 (device), read, then updated
+ *   adam_m, adam_v   2K floats each (device), Adam moments (zero before
+ *                    step 1), updated; step counts from 1
+ *   x, z, grad_y     rows x n at stride ld (device complex64): the input and
+ *                    the buffers for z and dE/dy
+ *   loss_dev         receives E (the loss at the coefficients before the
+ *                    update), or NULL
+ *   grad_coeffs      receives dE/dcoeffs (K complex64), or NULL
+ *   ws, ws_bytes     at least dpd_learn_step_ws_size(P) bytes
+ * Built for the shapes of the one-pass kernels (stages as in
+ * dpd_transmit_loss_grad; n a multiple of 256; x, z, grad_y 16-byte aligned
+ * with an even row stride): others are DPD_EUNSUPPORTED (use the separate
+ * calls).  coeffs_dev, adam_m, adam_v and grad_coeffs must not overlap.
+ * Allocates nothing; no host synchronization. */
+dpd_status dpd_learn_step_ws_size(const dpd_plan *P, size_t *bytes);
+dpd_status dpd_learn_step(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream, void *coeffs_dev,
+                          float *adam_m, float *adam_v, int32_t step, float lr, float beta1, float beta2,
+                          float eps, const void *x, void *z, void *grad_y, int64_t rows, int64_t n, int64_t ld,
+                          float scale, float *loss_dev, void *grad_coeffs, void *ws, size_t ws_bytes);
+
 /* ------------------------------------------------------- least squares --
  * The paper's coefficient estimate (section 2.2, Eq. 2): with the plan's
  * basis, row m of Psi is

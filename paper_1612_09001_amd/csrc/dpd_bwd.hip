@@ -149,45 +149,13 @@ __global__ void __launch_bounds__(kBlock) bwd_finalize(const float *__restrict__
                                                        CoefMap map, float2 *__restrict__ gcoef)
 {
     __shared__ double red[kBlock / 64][4];
-    const int L = map.L, NI = map.NI, E = 4 * L * NI + 2;
-    const int q = blockIdx.x;
-    const bool dc = q == L * NI;
-    const int base = 4 * q;
-    double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblk; b += kBlock) {
-        const float *pp = partials + (int64_t)b * E + base;
-        a[0] += (double)pp[0];
-        a[1] += (double)pp[1];
-        if (!dc) {
-            a[2] += (double)pp[2];
-            a[3] += (double)pp[3];
-        }
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) a[e] += __shfl_xor(a[e], off, 64);
-        if (lane == 0) red[wv][e] = a[e];
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
     double u[4];
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        u[e] = red[0][e];
-        for (int w = 1; w < kBlock / 64; ++w) u[e] += red[w][e];
-    }
-    if (dc) {
-        gcoef[(map.n_main + map.n_conj) * L] = make_float2((float)u[0], (float)u[1]);
-        return;
-    }
-    const int k = q / NI, j = q - k * NI;
-    const double u1 = u[0], u4 = u[1], u3 = u[2], u2 = u[3];
-    if (map.main_idx[j] >= 0)
-        gcoef[map.main_idx[j] * L + k] = make_float2((float)(u1 + u2), (float)(u3 - u4));
-    if (map.conj_idx[j] >= 0)
-        gcoef[(map.n_main + map.conj_idx[j]) * L + k] = make_float2((float)(u1 - u2), (float)(u3 + u4));
+    dcoef_block_sums(partials, nblk, map, blockIdx.x, red, u);
+    if (threadIdx.x != 0) return;
+    int idx[2];
+    float2 g[2];
+    const int c = dcoef_block_grads(map, blockIdx.x, u, idx, g);
+    for (int i = 0; i < c; ++i) gcoef[idx[i]] = g[i];
 }
 
 static bool spec_ok(const CoefMap &m) { return m.NI <= kSpecNI && m.L <= kSpecL; }

@@ -98,6 +98,69 @@ __device__ __forceinline__ void store_wave_totals(float (&acc)[E], float *out, i
     }
 }
 
+// FP64 sums of table entry q's four coefficient-gradient partials (two for
+// q = L NI, the c entry) over nblk blocks: each thread its strided share of
+// the blocks in order, then a fixed butterfly in each wave and the four waves
+// in order (bitwise reproducible).  u is valid in thread 0.
+__device__ __forceinline__ void dcoef_block_sums(const float *__restrict__ partials, int nblk, const CoefMap &map,
+                                                 int q, double (&red)[kBlock / 64][4], double (&u)[4])
+{
+    const int E = 4 * map.L * map.NI + 2;
+    const bool dc = q == map.L * map.NI;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += kBlock) {
+        const float *pp = partials + (int64_t)b * E + 4 * q;
+        a[0] += (double)pp[0];
+        a[1] += (double)pp[1];
+        if (!dc) {
+            a[2] += (double)pp[2];
+            a[3] += (double)pp[3];
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) a[e] += __shfl_xor(a[e], off, 64);
+        if (lane == 0) red[wv][e] = a[e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        u[e] = red[0][e];
+        for (int w = 1; w < kBlock / 64; ++w) u[e] += red[w][e];
+    }
+}
+
+// The chain rule from table entry q's sums to the coefficients of the
+// section 2.2 stacking (M = [[hr+gr, gi-hi], [hi+gi, hr-gr]], order 2j+1,
+// tap k): u1 = dE/dm00, u4 = dE/dm01, u3 = dE/dm10, u2 = dE/dm11,
+//   grad h = (u1 + u2) + j (u3 - u4),  grad hbar = (u1 - u2) + j (u3 + u4),
+//   grad c = sum G (q = L NI).
+// Returns how many coefficients (0..2) entry q feeds: idx[i], grad[i].
+__device__ __forceinline__ int dcoef_block_grads(const CoefMap &map, int q, const double (&u)[4], int (&idx)[2],
+                                                 float2 (&grad)[2])
+{
+    const int L = map.L, NI = map.NI;
+    if (q == L * NI) {
+        idx[0] = (map.n_main + map.n_conj) * L;
+        grad[0] = make_float2((float)u[0], (float)u[1]);
+        return 1;
+    }
+    const int k = q / NI, j = q - k * NI;
+    const double u1 = u[0], u4 = u[1], u3 = u[2], u2 = u[3];
+    int c = 0;
+    if (map.main_idx[j] >= 0) {
+        idx[c] = map.main_idx[j] * L + k;
+        grad[c++] = make_float2((float)(u1 + u2), (float)(u3 - u4));
+    }
+    if (map.conj_idx[j] >= 0) {
+        idx[c] = (map.n_main + map.conj_idx[j]) * L + k;
+        grad[c++] = make_float2((float)(u1 - u2), (float)(u3 + u4));
+    }
+    return c;
+}
+
 template <bool B>
 struct BwdTag {
     static constexpr bool value = B;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dpd_internal.h"
+#include "dpd_plan.h"
 
 namespace dpd {
 
@@ -121,6 +122,36 @@ __device__ __forceinline__ float2 cas_a_adjoint(const float (&ta)[kCasTA], int N
     return make_float2(__builtin_fmaf(2.f * qa, z1.x, px), __builtin_fmaf(2.f * qa, z1.y, py));
 }
 
+// FP64 total of nblk FP32 loss partials by one block of kBlock threads: each
+// thread its strided share in order, a fixed butterfly in each wave, then the
+// waves in order; the result is valid in thread 0.
+__device__ __forceinline__ double loss_block_total(const float *__restrict__ partials, int nblk,
+                                                   double (&red)[kBlock / 64])
+{
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) t += (double)partials[b];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    double u = red[0];
+    for (int w = 1; w < kBlock / 64; ++w) u += red[w];
+    return u;
+}
+
+// One Adam update (Kingma & Ba) of a real parameter from its gradient g;
+// bc1, bc2 are the bias corrections 1 - beta^step.
+__device__ __forceinline__ void adam_one(float &p, float g, float &m, float &v, float lr, float b1, float b2,
+                                         float eps, float bc1, float bc2)
+{
+    const float mi = __builtin_fmaf(b1, m, (1.f - b1) * g);
+    const float vi = __builtin_fmaf(b2, v, (1.f - b2) * g * g);
+    m = mi;
+    v = vi;
+    const float denom = __builtin_sqrtf(vi / bc2) + eps;
+    p -= (lr / bc1) * mi / denom;
+}
+
 __device__ __forceinline__ float2 cas_load(const float2 *__restrict__ r, int64_t m, int64_t n)
 {
     return (m >= 0 && m < n) ? r[m] : make_float2(0.f, 0.f);
@@ -150,6 +181,19 @@ hipError_t launch_loss_finalize(const float *partials, int nblk, double inv_n, f
 // the workspace bytes one call needs, and the FP64 finalisation of nblk
 // per-block partials into K complex gradients.
 size_t bwd_ws_bytes(const CoefMap &map);
+
+// Argument checks of the one-pass forward of the learning step (the stages
+// it is built for, sizes, alignment, overlaps; not the workspace).
+dpd_status check_transmit_forward(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, const void *x,
+                                  const void *z, const void *grad_y, int64_t rows, int64_t n, int64_t ld,
+                                  float scale);
+
+// The one-pass forward of the learning step (dpd_transmit.hip): launches it
+// with table M and loss partials into `partials`; *nblk receives the number
+// of partials written.  Arguments already validated.
+hipError_t launch_transmit_forward(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, hipStream_t hs,
+                                   const float *M, const void *x, void *z, void *grad_y, int64_t rows, int64_t n,
+                                   int64_t ld, float scale, float *partials, int *nblk);
 hipError_t launch_bwd_finalize(const float *partials, int nblk, const CoefMap &map, float2 *grad_coeffs,
                                hipStream_t st);
 

@@ -70,32 +70,16 @@ __global__ void __launch_bounds__(kBlock) loss_finalize(const float *__restrict_
                                                         float *__restrict__ loss)
 {
     __shared__ double red[kBlock / 64];
-    double t = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) t += (double)partials[b];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double u = red[0];
-        for (int w = 1; w < kBlock / 64; ++w) u += red[w];
-        *loss = (float)(u * inv_n);
-    }
+    const double u = loss_block_total(partials, nblk, red);
+    if (threadIdx.x == 0) *loss = (float)(u * inv_n);
 }
 
 __global__ void __launch_bounds__(kBlock) adam_kernel(float *__restrict__ p, const float *__restrict__ g,
                                                       float *__restrict__ m, float *__restrict__ v, int64_t count,
                                                       float lr, float b1, float b2, float eps, float bc1, float bc2)
 {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) {
-        const float gi = g[i];
-        const float mi = __builtin_fmaf(b1, m[i], (1.f - b1) * gi);
-        const float vi = __builtin_fmaf(b2, v[i], (1.f - b2) * gi * gi);
-        m[i] = mi;
-        v[i] = vi;
-        const float denom = __builtin_sqrtf(vi / bc2) + eps;
-        p[i] -= (lr / bc1) * mi / denom;
-    }
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock)
+        adam_one(p[i], g[i], m[i], v[i], lr, b1, b2, eps, bc1, bc2);
 }
 
 }  // namespace dpd

@@ -509,28 +509,65 @@ static int tx_occupancy(int NI, int L, int which, const void *kern)
     return v;
 }
 
+hipError_t launch_transmit_forward(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, hipStream_t hs,
+                                   const float *M, const void *x, void *z, void *grad_y, int64_t rows, int64_t n,
+                                   int64_t ld, float scale, float *partials, int *nblk)
+{
+    *nblk = 0;
+    const int64_t N = rows * n;
+    if (N == 0) return hipSuccess;
+    TxParams p;
+    p.M = M;
+    p.A = A->d_table;
+    p.B = B->d_table;
+    p.x = (const float2 *)x;
+    p.z = (float2 *)z;
+    p.gy = (float2 *)grad_y;
+    p.rows = rows;
+    p.n = n;
+    p.ld = rows > 1 ? ld : n;
+    p.qpr = (n + kTxQ - 1) / kTxQ;
+    p.scale = scale;
+    p.gscale = (float)(2.0 * scale / (double)N);
+    p.partials = partials;
+    p.vec = ((uintptr_t)x % 16 == 0 && (uintptr_t)z % 16 == 0 && (uintptr_t)grad_y % 16 == 0 &&
+             (rows == 1 || ld % 2 == 0)) ? 1 : 0;
+    // whole 512-sample chunks on 16-byte aligned rows: the streaming form,
+    // at most two resident blocks per CU; else one thread per eight
+    // samples.  One round of resident blocks either way (a second partial
+    // round would double the tail).
+    const bool stream_form = p.vec && n % 512 == 0;
+    const TxKernel kern = (stream_form ? tx_table().stream : tx_table().fwd)[P->map.NI - 1][P->map.L - 1];
+    const int occ = tx_occupancy(P->map.NI, P->map.L, stream_form ? 1 : 0, (const void *)kern);
+    const int64_t cap = (int64_t)num_cus() * (stream_form ? std::min(occ, 2) : occ);
+    const int64_t work = stream_form ? (rows * (n / 512) + 3) / 4 : (rows * p.qpr + kBlock - 1) / kBlock;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kLossBlocks, cap), work));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, hs, p);
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) *nblk = grid;
+    return e;
+}
+
 }  // namespace dpd
 
 using namespace dpd;
 
-DPD_EXPORT dpd_status dpd_transmit_loss_grad(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream,
-                                             const void *coeffs_dev, const void *x, void *z, int64_t rows, int64_t n,
-                                             int64_t ld, float scale, float *loss_dev, void *grad_y, void *ws,
-                                             size_t ws_bytes)
+namespace dpd {
+
+dpd_status check_transmit_forward(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, const void *x,
+                                  const void *z, const void *grad_y, int64_t rows, int64_t n, int64_t ld,
+                                  float scale)
 {
     if (P == nullptr || A == nullptr || B == nullptr) return DPD_EINVAL;
     if (A->map.L != 1) return DPD_EINVAL;
     if (rows < 0 || n < 0 || (rows > 1 && ld < n)) return DPD_EINVAL;
-    if (ws == nullptr || ws_bytes < kLossBlocks * sizeof(float) || (uintptr_t)ws % 4 != 0) return DPD_EINVAL;
     if (!std::isfinite(scale)) return DPD_EINVAL;
-    if (coeffs_dev != nullptr && (uintptr_t)coeffs_dev % 8 != 0) return DPD_EINVAL;
     if (A->map.NI != 1 || B->map.NI != kTxNIB || B->map.L != kTxLB || P->map.NI > kTxMaxNI ||
         P->map.L > kTxMaxL)
         return DPD_EUNSUPPORTED;
-    const int64_t N = rows * n;
-    if (N > 0) {
+    if (rows * n > 0) {
         if (x == nullptr || z == nullptr || grad_y == nullptr) return DPD_EINVAL;
-        for (const void *q : {x, (const void *)z, (const void *)grad_y})
+        for (const void *q : {x, z, grad_y})
             if ((uintptr_t)q % 8 != 0) return DPD_EINVAL;
         const size_t span = (size_t)(((rows - 1) * (rows > 1 ? ld : n) + n) * (int64_t)sizeof(float2));
         const auto lap = [&](const void *a, const void *b) {
@@ -539,6 +576,21 @@ DPD_EXPORT dpd_status dpd_transmit_loss_grad(dpd_plan *P, const dpd_plan *A, con
         };
         if (lap(z, x) || lap(grad_y, x) || lap(z, grad_y)) return DPD_EINVAL;
     }
+    return DPD_OK;
+}
+
+}  // namespace dpd
+
+DPD_EXPORT dpd_status dpd_transmit_loss_grad(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream,
+                                             const void *coeffs_dev, const void *x, void *z, int64_t rows, int64_t n,
+                                             int64_t ld, float scale, float *loss_dev, void *grad_y, void *ws,
+                                             size_t ws_bytes)
+{
+    const dpd_status st = check_transmit_forward(P, A, B, x, z, grad_y, rows, n, ld, scale);
+    if (st != DPD_OK) return st;
+    if (ws == nullptr || ws_bytes < kLossBlocks * sizeof(float) || (uintptr_t)ws % 4 != 0) return DPD_EINVAL;
+    if (coeffs_dev != nullptr && (uintptr_t)coeffs_dev % 8 != 0) return DPD_EINVAL;
+    const int64_t N = rows * n;
     const hipStream_t hs = (hipStream_t)stream;
     const float *M = P->d_table;
     if (coeffs_dev != nullptr) {
@@ -547,39 +599,10 @@ DPD_EXPORT dpd_status dpd_transmit_loss_grad(dpd_plan *P, const dpd_plan *A, con
         M = P->d_table_call;
     }
     int nblk = 0;
-    if (N > 0) {
-        TxParams p;
-        p.M = M;
-        p.A = A->d_table;
-        p.B = B->d_table;
-        p.x = (const float2 *)x;
-        p.z = (float2 *)z;
-        p.gy = (float2 *)grad_y;
-        p.rows = rows;
-        p.n = n;
-        p.ld = rows > 1 ? ld : n;
-        p.qpr = (n + kTxQ - 1) / kTxQ;
-        p.scale = scale;
-        p.gscale = (float)(2.0 * scale / (double)N);
-        p.partials = (float *)ws;
-        p.vec = ((uintptr_t)x % 16 == 0 && (uintptr_t)z % 16 == 0 && (uintptr_t)grad_y % 16 == 0 &&
-                 (rows == 1 || ld % 2 == 0)) ? 1 : 0;
-        // whole 512-sample chunks on 16-byte aligned rows: the streaming form,
-        // at most two resident blocks per CU; else one thread per eight
-        // samples.  One round of resident blocks either way (a second partial
-        // round would double the tail).
-        const bool stream_form = p.vec && n % 512 == 0;
-        const TxKernel kern = (stream_form ? tx_table().stream : tx_table().fwd)[P->map.NI - 1][P->map.L - 1];
-        const int occ = tx_occupancy(P->map.NI, P->map.L, stream_form ? 1 : 0, (const void *)kern);
-        const int64_t cap = (int64_t)num_cus() * (stream_form ? std::min(occ, 2) : occ);
-        const int64_t work = stream_form ? (rows * (n / 512) + 3) / 4 : (rows * p.qpr + kBlock - 1) / kBlock;
-        nblk = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kLossBlocks, cap), work));
-        hipLaunchKernelGGL(kern, dim3(nblk), dim3(kBlock), 0, hs, p);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e);
-    }
+    hipError_t e = launch_transmit_forward(P, A, B, hs, M, x, z, grad_y, rows, n, ld, scale, (float *)ws, &nblk);
+    if (e != hipSuccess) return hip_fail(e);
     if (loss_dev != nullptr) {
-        hipError_t e = launch_loss_finalize((const float *)ws, nblk, N > 0 ? 1.0 / (double)N : 0.0, loss_dev, hs);
+        e = launch_loss_finalize((const float *)ws, nblk, N > 0 ? 1.0 / (double)N : 0.0, loss_dev, hs);
         if (e != hipSuccess) return hip_fail(e);
     }
     return DPD_OK;

@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 
 #include "dpd.h"
 #include "dpd_bwd_kernels.h"
@@ -305,6 +306,84 @@ static int tb_occupancy(int NI, int L)
     return v;
 }
 
+// The one-pass backward into coefficient-gradient partials; *nblk receives
+// how many blocks wrote them.  Shapes already checked (whole chunks, aligned).
+static hipError_t launch_tb(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, hipStream_t hs, const void *x,
+                            const void *z, const void *grad_y, void *grad_z, float *partials, int64_t rows,
+                            int64_t n, int64_t rs, int *nblk)
+{
+    *nblk = 0;
+    if (rows * n == 0) return hipSuccess;
+    TbParams p;
+    p.A = A->d_table;
+    p.B = B->d_table;
+    p.x = (const float2 *)x;
+    p.z = (const float2 *)z;
+    p.gy = (const float2 *)grad_y;
+    p.gz = (float2 *)grad_z;
+    p.partials = partials;
+    p.rows = rows;
+    p.n = n;
+    p.ld = rs;
+    p.tpr = n / kTbChunk;
+    // one round of resident blocks, at most two per CU, each wave a run of chunks
+    const int NI = P->map.NI, L = P->map.L;
+    const int64_t cap = (int64_t)num_cus() * std::min(tb_occupancy(NI, L), 2);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(cap, (rows * p.tpr + 3) / 4));
+    hipLaunchKernelGGL(tb_table().k[NI - 1][L - 1], dim3(grid), dim3(kBlock), 0, hs, p);
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) *nblk = grid;
+    return e;
+}
+
+static bool tb_shapes_ok(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, const void *x, const void *z,
+                         const void *grad_y, const void *grad_z, int64_t n, int64_t rs)
+{
+    const bool stages = A->map.NI == 1 && B->map.NI == kTbNIB && B->map.L == kTbLB && P->map.NI <= kTbMaxNI &&
+                        P->map.L <= kTbMaxL;
+    const bool aligned = (uintptr_t)x % 16 == 0 && (uintptr_t)z % 16 == 0 && (uintptr_t)grad_y % 16 == 0 &&
+                         (uintptr_t)grad_z % 16 == 0 && rs % 2 == 0;
+    return stages && aligned && n % kTbChunk == 0;
+}
+
+// Learning-step finalisation in one launch: blocks 0 .. L NI sum the
+// coefficient-gradient partials of their table entry in FP64 (as dpd_backward
+// does), write the gradients (grad_coeffs may be NULL) and apply Adam to the
+// coefficients they belong to (as dpd_adam_step does: each coefficient has
+// exactly one entry); block L NI + 1 sums the loss partials.
+__global__ void __launch_bounds__(kBlock) learn_finalize(const float *__restrict__ dc, int nblk, CoefMap map,
+                                                         const float *__restrict__ lp, int nloss, double inv_n,
+                                                         float *__restrict__ loss, float2 *__restrict__ gcoef,
+                                                         float *__restrict__ params, float *__restrict__ m,
+                                                         float *__restrict__ v, float lr, float b1, float b2,
+                                                         float eps, float bc1, float bc2)
+{
+    __shared__ double red[kBlock / 64][4];
+    __shared__ double lred[kBlock / 64];
+    const int q = blockIdx.x;
+    if (q == map.L * map.NI + 1) {
+        const double u = loss_block_total(lp, nloss, lred);
+        if (threadIdx.x == 0 && loss != nullptr) *loss = (float)(u * inv_n);
+        return;
+    }
+    double u[4];
+    dcoef_block_sums(dc, nblk, map, q, red, u);
+    if (threadIdx.x != 0) return;
+    int idx[2];
+    float2 g[2];
+    const int c = dcoef_block_grads(map, q, u, idx, g);
+    for (int i = 0; i < c; ++i) {
+        if (gcoef != nullptr) gcoef[idx[i]] = g[i];
+        const int r = 2 * idx[i];
+        adam_one(params[r], g[i].x, m[r], v[r], lr, b1, b2, eps, bc1, bc2);
+        adam_one(params[r + 1], g[i].y, m[r + 1], v[r + 1], lr, b1, b2, eps, bc1, bc2);
+    }
+}
+
+// Workspace of dpd_learn_step: the loss partials, then (256-byte aligned) the
+// coefficient-gradient partials.
+static size_t learn_loss_bytes() { return ((size_t)kLossBlocks * sizeof(float) + 255) & ~(size_t)255; }
+
 }  // namespace dpd
 
 using namespace dpd;
@@ -334,12 +413,8 @@ DPD_EXPORT dpd_status dpd_transmit_backward(const dpd_plan *P, const dpd_plan *A
             if (lap(grad_z, x) || lap(grad_z, z) || lap(grad_z, grad_y)) return DPD_EINVAL;
         }
     }
-    const bool stages_ok = A->map.NI == 1 && B->map.NI == kTbNIB && B->map.L == kTbLB &&
-                           P->map.NI <= kTbMaxNI && P->map.L <= kTbMaxL;
-    const bool aligned = (uintptr_t)x % 16 == 0 && (uintptr_t)z % 16 == 0 && (uintptr_t)grad_y % 16 == 0 &&
-                         (uintptr_t)grad_z % 16 == 0 && rs % 2 == 0;
     const hipStream_t hs = (hipStream_t)stream;
-    if (!(stages_ok && aligned && n % kTbChunk == 0)) {
+    if (!tb_shapes_ok(P, A, B, x, z, grad_y, grad_z, n, rs)) {
         // other shapes: the two passes, dE/dz through the caller's grad_z
         if (N > 0 && grad_z == nullptr) return DPD_EUNSUPPORTED;
         dpd_status st = dpd_cascade_backward(A, B, stream, z, grad_y, grad_z, rows, n, ld);
@@ -348,27 +423,62 @@ DPD_EXPORT dpd_status dpd_transmit_backward(const dpd_plan *P, const dpd_plan *A
                             ld, ws, ws_bytes);
     }
     int nblk = 0;
-    if (N > 0) {
-        TbParams p;
-        p.A = A->d_table;
-        p.B = B->d_table;
-        p.x = (const float2 *)x;
-        p.z = (const float2 *)z;
-        p.gy = (const float2 *)grad_y;
-        p.gz = (float2 *)grad_z;
-        p.partials = (float *)ws;
-        p.rows = rows;
-        p.n = n;
-        p.ld = rs;
-        p.tpr = n / kTbChunk;
-        // one round of resident blocks, at most two per CU, each wave a run of chunks
-        const int NI = P->map.NI, L = P->map.L;
-        const int64_t cap = (int64_t)num_cus() * std::min(tb_occupancy(NI, L), 2);
-        nblk = (int)std::max<int64_t>(1, std::min<int64_t>(cap, (rows * p.tpr + 3) / 4));
-        hipLaunchKernelGGL(tb_table().k[NI - 1][L - 1], dim3(nblk), dim3(kBlock), 0, hs, p);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e);
-    }
-    hipError_t e = launch_bwd_finalize((const float *)ws, nblk, P->map, (float2 *)grad_coeffs, hs);
+    hipError_t e = launch_tb(P, A, B, hs, x, z, grad_y, grad_z, (float *)ws, rows, n, rs, &nblk);
+    if (e != hipSuccess) return hip_fail(e);
+    e = launch_bwd_finalize((const float *)ws, nblk, P->map, (float2 *)grad_coeffs, hs);
+    return e == hipSuccess ? DPD_OK : hip_fail(e);
+}
+
+DPD_EXPORT dpd_status dpd_learn_step_ws_size(const dpd_plan *P, size_t *bytes)
+{
+    if (P == nullptr || bytes == nullptr) return DPD_EINVAL;
+    *bytes = learn_loss_bytes() + bwd_ws_bytes(P->map);
+    return DPD_OK;
+}
+
+DPD_EXPORT dpd_status dpd_learn_step(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream,
+                                     void *coeffs_dev, float *adam_m, float *adam_v, int32_t step, float lr,
+                                     float beta1, float beta2, float eps, const void *x, void *z, void *grad_y,
+                                     int64_t rows, int64_t n, int64_t ld, float scale, float *loss_dev,
+                                     void *grad_coeffs, void *ws, size_t ws_bytes)
+{
+    dpd_status st = check_transmit_forward(P, A, B, x, z, grad_y, rows, n, ld, scale);
+    if (st != DPD_OK) return st;
+    if (coeffs_dev == nullptr || adam_m == nullptr || adam_v == nullptr || step < 1) return DPD_EINVAL;
+    if ((uintptr_t)coeffs_dev % 8 != 0 || (uintptr_t)adam_m % 4 != 0 || (uintptr_t)adam_v % 4 != 0 ||
+        (uintptr_t)grad_coeffs % 8 != 0)
+        return DPD_EINVAL;
+    if (!std::isfinite(lr) || !std::isfinite(beta1) || !std::isfinite(beta2) || !std::isfinite(eps))
+        return DPD_EINVAL;
+    const size_t need = learn_loss_bytes() + bwd_ws_bytes(P->map);
+    if (ws == nullptr || ws_bytes < need || (uintptr_t)ws % 4 != 0) return DPD_EINVAL;
+    // the K coefficients, their Adam moments and the gradient output must not overlap
+    const size_t kb = (size_t)P->K * sizeof(float2);
+    const auto lap = [kb](const void *a, const void *b) {
+        const uintptr_t u = (uintptr_t)a, v = (uintptr_t)b;
+        return a != nullptr && b != nullptr && u < v + kb && v < u + kb;
+    };
+    if (lap(coeffs_dev, adam_m) || lap(coeffs_dev, adam_v) || lap(adam_m, adam_v) || lap(grad_coeffs, coeffs_dev) ||
+        lap(grad_coeffs, adam_m) || lap(grad_coeffs, adam_v))
+        return DPD_EINVAL;
+    const int64_t rs = rows > 1 ? ld : n;
+    if (!tb_shapes_ok(P, A, B, x, z, grad_y, nullptr, n, rs)) return DPD_EUNSUPPORTED;
+    const hipStream_t hs = (hipStream_t)stream;
+    const int64_t N = rows * n;
+    hipError_t e = launch_prep(P->map, coeffs_dev, P->d_table_call, hs);
+    if (e != hipSuccess) return hip_fail(e);
+    float *lp = (float *)ws;
+    float *dc = (float *)((char *)ws + learn_loss_bytes());
+    int nloss = 0, nblk = 0;
+    e = launch_transmit_forward(P, A, B, hs, P->d_table_call, x, z, grad_y, rows, n, ld, scale, lp, &nloss);
+    if (e != hipSuccess) return hip_fail(e);
+    e = launch_tb(P, A, B, hs, x, z, grad_y, nullptr, dc, rows, n, rs, &nblk);
+    if (e != hipSuccess) return hip_fail(e);
+    const float bc1 = (float)(1.0 - std::pow((double)beta1, step));
+    const float bc2 = (float)(1.0 - std::pow((double)beta2, step));
+    hipLaunchKernelGGL(learn_finalize, dim3((uint32_t)(P->map.L * P->map.NI + 2)), dim3(kBlock), 0, hs, dc, nblk,
+                       P->map, lp, nloss, N > 0 ? 1.0 / (double)N : 0.0, loss_dev, (float2 *)grad_coeffs,
+                       (float *)coeffs_dev, adam_m, adam_v, lr, beta1, beta2, eps, bc1, bc2);
+    e = hipGetLastError();
     return e == hipSuccess ? DPD_OK : hip_fail(e);
 }

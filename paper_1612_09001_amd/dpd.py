@@ -80,6 +80,10 @@ _SIGS = {
     "dpd_transmit_loss_grad": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, _vp, _vp, _vp,
                                ctypes.c_size_t],
     "dpd_transmit_backward": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64, _i64, _vp, ctypes.c_size_t],
+    "dpd_learn_step_ws_size": [_vp, ctypes.POINTER(ctypes.c_size_t)],
+    "dpd_learn_step": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                       ctypes.c_float, _vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, _vp, _vp, _vp,
+                       ctypes.c_size_t],
     "dpd_adam_step": [_vp, _vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float,
                       ctypes.c_float, ctypes.c_float],
     "dpd_ls_ws_size": [_vp, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
@@ -300,6 +304,19 @@ def dpd_transmit_backward(plan_p, plan_a, plan_b, stream, x_ptr, z_ptr, gy_ptr, 
     _check(lib().dpd_transmit_backward(plan_p, plan_a, plan_b, stream, x_ptr, z_ptr, gy_ptr, gz_ptr, gc_ptr,
                                        int(rows), int(n), int(ld), ws_ptr, int(ws_bytes)),
            "dpd_transmit_backward")
+
+
+def dpd_learn_step_ws_size(plan_p) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().dpd_learn_step_ws_size(plan_p, ctypes.byref(b)), "dpd_learn_step_ws_size")
+    return b.value
+
+
+def dpd_learn_step(plan_p, plan_a, plan_b, stream, coeffs_ptr, m_ptr, v_ptr, step, lr, beta1, beta2, eps, x_ptr,
+                   z_ptr, gy_ptr, rows, n, ld, scale, loss_ptr, gc_ptr, ws_ptr, ws_bytes):
+    _check(lib().dpd_learn_step(plan_p, plan_a, plan_b, stream, coeffs_ptr, m_ptr, v_ptr, int(step), float(lr),
+                                float(beta1), float(beta2), float(eps), x_ptr, z_ptr, gy_ptr, int(rows), int(n),
+                                int(ld), float(scale), loss_ptr, gc_ptr, ws_ptr, int(ws_bytes)), "dpd_learn_step")
 
 
 def dpd_adam_step(stream, p_ptr, g_ptr, m_ptr, v_ptr, count, step, lr, beta1=0.9, beta2=0.999,

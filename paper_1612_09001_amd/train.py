@@ -63,7 +63,10 @@ class FusedTrainer:
         self.t = 0
         ws = max(_dpd.dpd_backward_ws_size(p.handle, self.rows, self.n)
                  for p in (self.plan, self.pa.iq, self.pa.pa))
-        self.ws_bytes = max(ws, _dpd.dpd_loss_ws_size(self.rows * self.n))
+        self.ws_bytes = max(ws, _dpd.dpd_loss_ws_size(self.rows * self.n), _dpd.dpd_learn_step_ws_size(self.plan.handle))
+        # the whole step in one library call where its one-pass kernels apply
+        # (whole 256-sample chunks; torch's allocations are 16-byte aligned)
+        self.one_call = self.one_pass and self.n % 256 == 0
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
 
     def step(self):
@@ -73,6 +76,12 @@ class FusedTrainer:
         R, N, ld = self.rows, self.n, self.n
         P = lambda t: t.data_ptr()
         iq, pa = self.pa.iq.handle, self.pa.pa.handle
+        if self.fused_transmitter and self.one_call:
+            self.t += 1
+            _dpd.dpd_learn_step(self.plan.handle, iq, pa, st, P(self.coeffs), P(self.m), P(self.v), self.t, self.lr,
+                                self.betas[0], self.betas[1], self.eps, P(self.x), P(self.z), P(self.gy), R, N, ld,
+                                1.0 / self.pa.gain, P(self.loss), P(self.gc), P(self.ws), self.ws_bytes)
+            return self.loss
         if self.fused_transmitter and self.one_pass:
             # forward in one pass, backward in another: dE/dz stays on chip where
             # the shapes allow (else dpd_transmit_backward goes through self.gz)

@@ -321,3 +321,28 @@ def test_transmit_backward_bad_arguments(torch):
             call(**kw)
         assert e.value.status == dpd.DPD_EINVAL, kw
     torch.cuda.synchronize()
+
+
+def test_learning_passes_on_empty_input(torch):
+    """No samples (rows = 0 or n = 0): the one-pass forward reports a zero
+    loss and the one-pass backward a zero gradient, touching no sample."""
+    from paper_1612_09001_amd import dpd
+
+    A, B = _stages("synthetic_pa")
+    mo = co = [1, 3, 5, 7]
+    P = dpd.Plan(mo, co, 6, signals.aph_coeffs(mo, co, 6, config_id=81))
+    pa_, pb_ = dpd.Plan(*A), dpd.Plan(*B)
+    st = dpd.current_stream()
+    wsb = max(dpd.dpd_backward_ws_size(P.handle, 1, 256), dpd.dpd_loss_ws_size(256))
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    x = torch.zeros(256, dtype=torch.complex64, device="cuda")
+    z, gy = torch.zeros_like(x), torch.zeros_like(x)
+    for rows, n in ((0, 256), (4, 0)):
+        loss = torch.full((1,), 7.0, dtype=torch.float32, device="cuda")
+        gc = torch.full((P.K,), complex(7.0, 7.0), dtype=torch.complex64, device="cuda")
+        dpd.dpd_transmit_loss_grad(P.handle, pa_.handle, pb_.handle, st, 0, x.data_ptr(), z.data_ptr(), rows, n,
+                                   max(n, 1), 0.1, loss.data_ptr(), gy.data_ptr(), ws.data_ptr(), wsb)
+        dpd.dpd_transmit_backward(P.handle, pa_.handle, pb_.handle, st, x.data_ptr(), z.data_ptr(), gy.data_ptr(),
+                                  0, gc.data_ptr(), rows, n, max(n, 1), ws.data_ptr(), wsb)
+        torch.cuda.synchronize()
+        assert float(loss.item()) == 0.0 and not np.any(gc.cpu().numpy()), (rows, n)

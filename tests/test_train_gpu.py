@@ -30,10 +30,10 @@ def _rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-# n = 5000: both passes of the step in their general forms; 5120: the forward
-# general, the backward in one pass (whole 256-sample chunks); 8192: both in
-# their one-pass streaming forms.
-@pytest.mark.parametrize("n", [5000, 5120, 8192])
+# n = 5000: both passes of the step in their general forms (separate calls);
+# 4864 = 19 x 256: the whole step in one call, the forward in its general
+# form, the backward in one pass; 8192: one call, both streaming forms.
+@pytest.mark.parametrize("n", [5000, 4864, 8192])
 def test_fused_gradient_matches_fp64_chain(torch, orc, n):
     import oracle.pa as opa
     from paper_1612_09001_amd.train import FusedTrainer
@@ -182,3 +182,80 @@ def test_gradient_learned_suppression(torch, orc, generator):
           % (generator, g0, o0, g1, o1))
     assert abs(g0 - o0) <= 0.5 and abs(g1 - o1) <= 0.5, (g0, o0, g1, o1)
     assert g1 <= g0 - 10.0, (g0, g1)
+
+
+def test_learn_step_equals_separate_calls(torch):
+    """dpd_learn_step against dpd_transmit_loss_grad + dpd_transmit_backward +
+    dpd_adam_step over three steps: loss, gradient, coefficients and both Adam
+    moments bitwise equal after every step."""
+    from paper_1612_09001_amd import dpd
+    from paper_1612_09001_amd.pa import SyntheticPA
+
+    rows, n = 4, 8192
+    _, xd = _data(torch, rows, n, cid=7)
+    h0 = signals.aph_coeffs(*ORDERS, L, config_id=51)
+    h0[0] += 1.0
+    P1, P2 = dpd.Plan(*ORDERS, L, h0), dpd.Plan(*ORDERS, L, h0)
+    pa = SyntheticPA()
+    iq, pb = pa.iq.handle, pa.pa.handle
+    K = P1.K
+    st = dpd.current_stream()
+    state = []
+    for _ in range(2):
+        state.append({"c": torch.from_numpy(h0.astype(np.complex64)).cuda(),
+                      "m": torch.zeros(2 * K, dtype=torch.float32, device="cuda"),
+                      "v": torch.zeros(2 * K, dtype=torch.float32, device="cuda"),
+                      "gc": torch.zeros(K, dtype=torch.complex64, device="cuda"),
+                      "loss": torch.zeros(1, dtype=torch.float32, device="cuda"),
+                      "z": torch.empty_like(xd), "gy": torch.empty_like(xd)})
+    wsb = max(dpd.dpd_learn_step_ws_size(P1.handle), dpd.dpd_backward_ws_size(P2.handle, rows, n),
+              dpd.dpd_loss_ws_size(rows * n))
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    a, b = state
+    ptr = lambda t: t.data_ptr()
+    for step in (1, 2, 3):
+        dpd.dpd_learn_step(P1.handle, iq, pb, st, ptr(a["c"]), ptr(a["m"]), ptr(a["v"]), step, 0.01, 0.9, 0.999, 1e-8,
+                           ptr(xd), ptr(a["z"]), ptr(a["gy"]), rows, n, n, 0.1, ptr(a["loss"]), ptr(a["gc"]), ptr(ws),
+                           wsb)
+        dpd.dpd_transmit_loss_grad(P2.handle, iq, pb, st, ptr(b["c"]), ptr(xd), ptr(b["z"]), rows, n, n, 0.1,
+                                   ptr(b["loss"]), ptr(b["gy"]), ptr(ws), wsb)
+        dpd.dpd_transmit_backward(P2.handle, iq, pb, st, ptr(xd), ptr(b["z"]), ptr(b["gy"]), 0, ptr(b["gc"]), rows, n,
+                                  n, ptr(ws), wsb)
+        dpd.dpd_adam_step(st, ptr(b["c"]), ptr(b["gc"]), ptr(b["m"]), ptr(b["v"]), 2 * K, step, 0.01, 0.9, 0.999,
+                          1e-8)
+        torch.cuda.synchronize()
+        for key in ("loss", "gc", "c", "m", "v", "z", "gy"):
+            assert torch.equal(a[key], b[key]), (step, key)
+
+
+def test_learn_step_arguments(torch):
+    from paper_1612_09001_amd import dpd
+    from paper_1612_09001_amd.pa import SyntheticPA
+
+    rows, n = 2, 1024
+    _, xd = _data(torch, rows, n, cid=8)
+    h0 = signals.identity_coeffs(*ORDERS, L)
+    P = dpd.Plan(*ORDERS, L, h0)
+    pa = SyntheticPA()
+    c = torch.from_numpy(h0.astype(np.complex64)).cuda()
+    m = torch.zeros(2 * P.K, dtype=torch.float32, device="cuda")
+    v = torch.zeros_like(m)
+    z, gy = torch.empty_like(xd), torch.empty_like(xd)
+    wsb = dpd.dpd_learn_step_ws_size(P.handle)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    st = dpd.current_stream()
+    ptr = lambda t: t.data_ptr()
+
+    def call(step=1, cc=None, mm=None, nn=n, ld=n, b=wsb, gc=0):
+        dpd.dpd_learn_step(P.handle, pa.iq.handle, pa.pa.handle, st, cc if cc is not None else ptr(c),
+                           mm if mm is not None else ptr(m), ptr(v), step, 1e-3, 0.9, 0.999, 1e-8, ptr(xd), ptr(z),
+                           ptr(gy), rows, nn, ld, 0.1, 0, gc, ptr(ws), b)
+
+    call()
+    for kw, status in (({"step": 0}, dpd.DPD_EINVAL), ({"mm": ptr(v)}, dpd.DPD_EINVAL),
+                       ({"gc": ptr(c)}, dpd.DPD_EINVAL), ({"b": wsb - 4}, dpd.DPD_EINVAL),
+                       ({"nn": 1000, "ld": n}, dpd.DPD_EUNSUPPORTED)):
+        with pytest.raises(dpd.DPDError) as e:
+            call(**kw)
+        assert e.value.status == status, kw
+    torch.cuda.synchronize()
