@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kBlock) bwd_dc_generic(BwdParams p, int NI, in
 // Coefficient-gradient finalisation: block q sums, in FP64, the partials of
 // the four entries of table matrix q = k*NI + j (block L*NI: the two entries
 // of c) over all nblk producer blocks -- thread t takes producers t, t + 256,
-// ... in order, then a fixed butterfly in each wave and the four waves in
+// ... in order, then the DPP lane sum of each wave and the four waves in
 // order, so the result is bitwise reproducible -- and applies the chain rule
 // through M = [[hr+gr, gi-hi], [hi+gi, hr-gr]] to the main and conjugate
 // coefficients of order 2j+1, tap k (section 2.2 layout):

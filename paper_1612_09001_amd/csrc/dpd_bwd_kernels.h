@@ -21,6 +21,7 @@
 #pragma once
 
 #include "dpd_fwd_kernels.h"
+#include "dpd_reduce.h"
 
 namespace dpd {
 
@@ -52,39 +53,6 @@ void register_bwd_ni8(BwdTable &);
 
 constexpr int kBwdS = 4;   // consecutive samples per lane
 
-// Sum over the 64 lanes of a wave (butterfly; every lane gets the total).
-__device__ __forceinline__ float wave_sum(float v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// One DPP step of a lane reduction: x from the lane that CTRL selects (rows
-// outside RMASK read zero).
-template <int CTRL, int RMASK>
-__device__ __forceinline__ float dpp_from(float x)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, RMASK, 0xf, false));
-}
-
-// Sum over the 64 lanes, complete in lane 63 (the other lanes hold partial
-// sums), by DPP row operations -- no LDS round trips: quad sums (quad_perm
-// 1,0,3,2 and 2,3,0,1), 8- and 16-lane sums (row_half_mirror, row_mirror),
-// then rows 1 and 3 add rows 0 and 2 (row_bcast:15) and rows 2 and 3 add the
-// sum of rows 0..1 (row_bcast:31).  Fixed order: the same inputs give the
-// same bits.
-__device__ __forceinline__ float wave_sum_to_lane63(float v)
-{
-    v += dpp_from<0xB1, 0xf>(v);
-    v += dpp_from<0x4E, 0xf>(v);
-    v += dpp_from<0x141, 0xf>(v);
-    v += dpp_from<0x140, 0xf>(v);
-    v += dpp_from<0x142, 0xa>(v);
-    v += dpp_from<0x143, 0xc>(v);
-    return v;
-}
-
 // The wave totals of E per-lane accumulators into out[0..E) (LDS): every
 // accumulator reduced in place, then lane 63 stores them all.
 template <int E>
@@ -100,7 +68,7 @@ __device__ __forceinline__ void store_wave_totals(float (&acc)[E], float *out, i
 
 // FP64 sums of table entry q's four coefficient-gradient partials (two for
 // q = L NI, the c entry) over nblk blocks: each thread its strided share of
-// the blocks in order, then a fixed butterfly in each wave and the four waves
+// the blocks in order, then the DPP lane sum of each wave and the four waves
 // in order (bitwise reproducible).  u is valid in thread 0.
 __device__ __forceinline__ void dcoef_block_sums(const float *__restrict__ partials, int nblk, const CoefMap &map,
                                                  int q, double (&red)[kBlock / 64][4], double (&u)[4])
@@ -120,9 +88,8 @@ __device__ __forceinline__ void dcoef_block_sums(const float *__restrict__ parti
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) a[e] += __shfl_xor(a[e], off, 64);
-        if (lane == 0) red[wv][e] = a[e];
+        a[e] = wave_sum_to_lane63(a[e]);
+        if (lane == 63) red[wv][e] = a[e];
     }
     __syncthreads();
 #pragma unroll

@@ -6,6 +6,7 @@
 
 #include "dpd_internal.h"
 #include "dpd_plan.h"
+#include "dpd_reduce.h"
 
 namespace dpd {
 
@@ -123,16 +124,15 @@ __device__ __forceinline__ float2 cas_a_adjoint(const float (&ta)[kCasTA], int N
 }
 
 // FP64 total of nblk FP32 loss partials by one block of kBlock threads: each
-// thread its strided share in order, a fixed butterfly in each wave, then the
+// thread its strided share in order, the DPP lane sum of each wave, then the
 // waves in order; the result is valid in thread 0.
 __device__ __forceinline__ double loss_block_total(const float *__restrict__ partials, int nblk,
                                                    double (&red)[kBlock / 64])
 {
     double t = 0.0;
     for (int b = threadIdx.x; b < nblk; b += kBlock) t += (double)partials[b];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    t = wave_sum_to_lane63(t);
+    if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = t;
     __syncthreads();
     double u = red[0];
     for (int w = 1; w < kBlock / 64; ++w) u += red[w];

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(kBlock) loss_kernel(const float2 *__restrict__
 }
 
 // FP64 sum of the block partials: thread t takes partials t, t + 256, ... in
-// order, then a fixed butterfly in each wave and the four waves in order
+// order, then the DPP lane sum of each wave and the four waves in order
 // (bitwise reproducible for a given partial count).
 __global__ void __launch_bounds__(kBlock) loss_finalize(const float *__restrict__ partials, int nblk, double inv_n,
                                                         float *__restrict__ loss)
