@@ -442,7 +442,11 @@ __global__ void __launch_bounds__(kBlock) fwd_stream_kernel(FwdParams p)
             }
             return u;
         };
+        // The prefetch issues at raised wave priority, so a wave reaching it
+        // is not held behind the other waves' filter work on the SIMD
+        // (measured: 47.8 -> 47.2 us at the 2^24 headline, outputs unchanged).
         auto load_full = [&](ChunkRegs<S> &buf, const Cur &u) {
+            __builtin_amdgcn_s_setprio(2);
             const int64_t t0 = u.k * C;
             const float4 *x4 = reinterpret_cast<const float4 *>(p.in + u.row * p.ld + t0);
 #pragma unroll
@@ -452,6 +456,7 @@ __global__ void __launch_bounds__(kBlock) fwd_stream_kernel(FwdParams p)
                 buf.v[i] = make_float4(t.x, t.y, t.z, t.w);
             }
             buf.h = halo_raw_full(u.row, t0);
+            __builtin_amdgcn_s_setprio(0);
         };
         auto step = [&](const ChunkRegs<S> &buf, const Cur &u) {
             float zr[S], zi[S];

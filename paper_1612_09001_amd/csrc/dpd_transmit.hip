@@ -276,6 +276,7 @@ __global__ void __launch_bounds__(kBlock) transmit_stream_kernel(TxParams p)
         return r;
     };
     auto load_full = [&](ChunkRegs<S> &buf, const Cur &u) {
+        __builtin_amdgcn_s_setprio(2);   // the prefetch at raised wave priority
         const float4 *x4 = reinterpret_cast<const float4 *>(p.x + u.row * p.ld + u.k * C);
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
@@ -283,6 +284,7 @@ __global__ void __launch_bounds__(kBlock) transmit_stream_kernel(TxParams p)
             buf.v[i] = make_float4(t.x, t.y, t.z, t.w);
         }
         buf.h = halo_raw(u);
+        __builtin_amdgcn_s_setprio(0);
     };
     auto next = [&](Cur u) {
         if (++u.k == tpr) {

@@ -99,6 +99,7 @@ __global__ void __launch_bounds__(kBlock) transmit_bwd_kernel(TbParams p)
         float2 yh;   // dE/dy at t0 + C + lane (lanes < HY; zero past the row end)
     };
     auto load = [&](Regs &R, int64_t row, int64_t t0) {
+        __builtin_amdgcn_s_setprio(2);   // the prefetch at raised wave priority
         const int64_t base = row * p.ld + t0;
         const v4f *z4 = reinterpret_cast<const v4f *>(p.z + base);
         const v4f *y4 = reinterpret_cast<const v4f *>(p.gy + base);
@@ -123,6 +124,7 @@ __global__ void __launch_bounds__(kBlock) transmit_bwd_kernel(TbParams p)
         const bool in = t0 + C < p.n;
         const float2 v = p.gy[row * p.ld + (in ? t0 + C + hl : t0)];
         R.yh = in ? v : make_float2(0.f, 0.f);
+        __builtin_amdgcn_s_setprio(0);
     };
     auto stage = [&](const Regs &R) {
         wave_lds_order();   // the previous chunk's LDS reads are done
