@@ -310,7 +310,16 @@ def leg_config3(torch, dpd, signals, steps=50):
             "valu_frac_published": round(tfl / VALU_FP32_PEAK_TFLOPS, 4), "tune": plan.get_tune()}
 
 
-def leg_config4(torch, dpd, signals, reps=20):
+def _steady_us(fn, rounds=5, warmup=10, iters=30):
+    """Median over `rounds` of the mean time per call of `iters` back-to-back
+    calls after `warmup` untimed ones (HIP events): the steady-state time of a
+    launch long enough that the clock state of the first calls matters."""
+    from paper_1612_09001_amd import autotune
+
+    return float(np.median([autotune.time_us(fn, warmup=warmup, iters=iters) for _ in range(rounds)]))
+
+
+def leg_config4(torch, dpd, signals):
     """256 streams, lengths U[2^14, 2^20], own coefficients, P_max in {5,7,9},
     L in {2..8}: one persistent launch (graph-replayed) vs 256 launches."""
     from paper_1612_09001_amd import autotune, batch
@@ -318,18 +327,18 @@ def leg_config4(torch, dpd, signals, reps=20):
     wl = batch.BatchWorkload(signals.batch_specs(), config_id=4)
     tune, b = autotune.tune_batch(wl)
     total = wl.samples()
-    t_direct = autotune.time_us(b.apply, iters=reps)
-    t_each = autotune.time_us(b.apply_each, iters=reps)
+    t_direct = _steady_us(b.apply)
+    t_each = _steady_us(b.apply_each)
     g = torch.cuda.CUDAGraph()
     b.apply()
     torch.cuda.synchronize()
     with torch.cuda.graph(g):
         b.apply()
-    t_graph = autotune.time_us(g.replay, iters=reps)
+    t_graph = _steady_us(g.replay)
     ge = torch.cuda.CUDAGraph()
     with torch.cuda.graph(ge):
         b.apply_each()
-    t_graph_each = autotune.time_us(ge.replay, iters=reps)
+    t_graph_each = _steady_us(ge.replay)
     gbs = BYTES_PER_SAMPLE * total / (t_graph * 1e-6) / 1e9
     # every output of every stream (from the last graph replay) against the oracle
     torch.cuda.synchronize()
