@@ -118,3 +118,19 @@ def test_batch_rejects_overlapping_streams(lib):
     # need a device: DPD_OK on a GPU, DPD_EHIP without one)
     assert create([desc(0x10000, 0x20000, 100), desc(0x10000, 0x20000 + 8 * 100, 100)]) != dpd.DPD_EINVAL
     assert create(many) != dpd.DPD_EINVAL
+
+
+def test_learning_entry_points_reject_on_the_host(lib):
+    """The learning-step entry points reject missing plans, absent outputs and
+    workspaces before any device call (fake, never dereferenced addresses)."""
+    fake = ctypes.c_void_p(1 << 20)
+    sz = ctypes.c_size_t()
+    assert lib.dpd_learn_step_ws_size(None, ctypes.byref(sz)) == dpd.DPD_EINVAL
+    assert lib.dpd_transmit_backward(None, None, None, None, fake, fake, fake, None, fake, 1, 256, 256, fake,
+                                     1 << 20) == dpd.DPD_EINVAL
+    assert lib.dpd_transmit_loss_grad(None, None, None, None, None, fake, fake, 1, 256, 256, ctypes.c_float(0.1),
+                                      None, fake, fake, 1 << 20) == dpd.DPD_EINVAL
+    assert lib.dpd_learn_step(None, None, None, None, fake, fake, fake, 1, ctypes.c_float(1e-3),
+                              ctypes.c_float(0.9), ctypes.c_float(0.999), ctypes.c_float(1e-8), fake, fake, fake,
+                              1, 256, 256, ctypes.c_float(0.1), None, None, fake, 1 << 20) == dpd.DPD_EINVAL
+    assert lib.dpd_set_coeffs_async(None, None, None) == dpd.DPD_EINVAL
