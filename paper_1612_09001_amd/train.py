@@ -1,22 +1,27 @@
 """Learning predistorter coefficients through the fixed synthetic PA.
 
 ``FusedTrainer.step()`` runs one full-batch gradient step entirely in libdpd
-kernels, on buffers allocated once:
+kernels, on buffers allocated once.  With rows of whole 256-sample chunks it
+is one library call, ``dpd_learn_step`` (four launches):
 
-  z, E, dE/dy                the predistorter (coefficients read from the
-                             device), the synthetic transmitter u = IQ(z),
-                             y = PA(u) (pa.py) and the loss E = mean |y/G - x|^2
-                             with its gradient in one kernel
-                             (dpd_transmit_loss_grad: u and y are never
-                             stored, z is written once for the adjoint)
-  dE/dz                      adjoint of PA and IQ (dpd_cascade_backward)
-  dE/dcoeffs                 adjoint of the predistorter (coefficients only)
-  Adam                       update of the K complex coefficients
+  table                      the predistorter's coefficients precombined
+  z, E, dE/dy                the predistorter, the synthetic transmitter
+                             u = IQ(z), y = PA(u) (pa.py) and the loss
+                             E = mean |y/G - x|^2 with its gradient in one
+                             pass (u and y never stored, z written once)
+  dE/dcoeffs                 the adjoint of PA and IQ and the coefficient
+                             gradient of the predistorter in one pass (dE/dz
+                             never stored)
+  finalisation + Adam        loss and gradient summed in FP64, Adam applied
+                             to the K complex coefficients in place
 
-``one_pass=False`` runs the predistorter as its own launch before the fused
-transmitter (dpd_apply_coeffs, then dpd_cascade_loss_grad);
-``fused_transmitter=False`` runs the transmitter and its adjoint as separate
-launches per stage (IQ, PA, loss; PA and IQ adjoints) instead.
+Other row lengths run the same passes as separate calls
+(dpd_transmit_loss_grad, dpd_transmit_backward through a dE/dz buffer,
+dpd_adam_step).  ``one_pass=False`` runs the predistorter as its own launch
+before the fused transmitter (dpd_apply_coeffs, dpd_cascade_loss_grad,
+dpd_cascade_backward, dpd_backward); ``fused_transmitter=False`` runs the
+transmitter and its adjoint as separate launches per stage (IQ, PA, loss; PA
+and IQ adjoints) instead.
 
 ``AutogradTrainer`` is the same step through ``torch.autograd`` with the
 predistorter and both PA stages as ``DPDFunction`` nodes (hand-written
