@@ -655,6 +655,36 @@ def leg_ls(torch, dpd, signals, reps=5):
     return out
 
 
+def learn_step_work(NI, L, NIB=3, LB=3):
+    """Arithmetic (flops, a multiply-add counted as two) and HBM bytes per
+    sample of one learning step with the one-pass kernels: the predistorter
+    (NI power levels, L taps), the memoryless I/Q stage, the PA (NIB levels,
+    LB taps) and the loss forward; the two stage adjoints and the
+    predistorter's coefficient gradient backward.  Bytes: x read and z, dE/dy
+    written forward; x, z, dE/dy read backward."""
+    fwd = ((8 * NI * L + 3)                  # predistorter: 2x2 matrices by Horner in |x|^2, and |x|^2
+           + (8 + 3)                         # I/Q stage (one level) and |u|^2
+           + (8 * NIB * LB + 3)              # PA and the |u|^2 it reads
+           + 10)                             # residual, squared error, dE/dy
+    bwd = ((8 + 3)                           # u = A(z) again and |u|^2
+           + 8 * NIB * LB                    # U_j = sum_k M^T g for the PA
+           + 10 * (NIB - 1) + 4              # P + 2 Q u by Horner
+           + 8                               # I/Q stage transpose
+           + 8 * NI * L + 6 * (NI - 1) + 4)  # coefficient gradient, powers of |x|^2 times v, sum of G
+    return fwd, bwd, 48
+
+
+def _learn_roofline(samples, ms, orders, L):
+    ni = (max(orders) + 1) // 2
+    fwd, bwd, nbytes = learn_step_work(ni, L)
+    t = ms * 1e-3
+    return {"flops_per_sample": fwd + bwd, "bytes_per_sample": nbytes,
+            "valu_tflops": round(samples * (fwd + bwd) / t / 1e12, 2),
+            "valu_frac_nonpacked": round(samples * (fwd + bwd) / t / 1e12 / VALU_FP32_NONPACKED_TFLOPS, 4),
+            "hbm_frac": round(samples * nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "the whole step (four launches) against the non-packed FP32 VALU peak at 2.4 GHz and HBM peak"}
+
+
 def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
     """64 x 2^18 samples, DPD orders {1,3,5,7} both branches, L = 6, identity
     start, synthetic PA, loss mean|y/10 - x|^2, Adam lr 1e-3: the fused step
@@ -756,6 +786,7 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
     return {"workload": "64x2^18 OFDM-like, DPD {1,3,5,7} main+conj L=6, synthetic PA, Adam 1e-3",
             "accuracy_step0": acc, "suppression": sup,
             "grad_step_ms_fused": round(med(fused_ms), 4),
+            "grad_step_roofline": _learn_roofline(rows * n, med(fused_ms), orders, L),
             "grad_step_ms_fused_transmitter_per_stage": round(med(stage_ms), 4),
             "per_stage_vs_fused_loss_rel_max_first_50": float("%.3g" % float(np.max(
                 np.abs(np.array(stage_loss) - np.array(fused_loss[:50])) / np.array(fused_loss[:50])))),
