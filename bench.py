@@ -197,13 +197,22 @@ def _rotating(torch, x_host, total_bytes=ROTATE_BYTES):
     return xs, zs
 
 
+WARM_S = 0.05   # the GPU clocks settle after ~30 ms of load (and drop again while the host works)
+
+
 def _time_launches(torch, launch, nbuf, steps, warmup):
     """Back-to-back launches between one pair of HIP events on the launch
     stream (torch's current stream); returns wall seconds and mean ms per
-    launch (kernel time plus the inter-launch gap of a busy queue)."""
-    for i in range(warmup):
-        launch(i % nbuf)
-    torch.cuda.synchronize()
+    launch (kernel time plus the inter-launch gap of a busy queue).  Before
+    timing: `warmup` launches, repeated until at least WARM_S of load has
+    run, so every leg is timed at settled clocks."""
+    t0 = time.perf_counter()
+    while True:
+        for i in range(max(1, warmup)):
+            launch(i % nbuf)
+        torch.cuda.synchronize()
+        if time.perf_counter() - t0 >= WARM_S:
+            break
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -312,10 +321,17 @@ def leg_config3(torch, dpd, signals, steps=50):
 
 def _steady_us(fn, rounds=5, warmup=10, iters=30):
     """Median over `rounds` of the mean time per call of `iters` back-to-back
-    calls after `warmup` untimed ones (HIP events): the steady-state time of a
-    launch long enough that the clock state of the first calls matters."""
+    calls after `warmup` untimed ones (HIP events), the first round after at
+    least WARM_S of load: the steady-state time of a launch long enough that
+    the clock state of the first calls matters."""
+    import torch
     from paper_1612_09001_amd import autotune
 
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < WARM_S:
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
     return float(np.median([autotune.time_us(fn, warmup=warmup, iters=iters) for _ in range(rounds)]))
 
 
