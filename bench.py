@@ -742,14 +742,27 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
     acc = {"loss_rel": float("%.3g" % (abs(loss0 - E_ref) / E_ref)),
            "gradient": gate_dcoef(gc0, g_ref, entry_max=1e-4, rel_max=1e-4)}
     acc["pass"] = bool(acc["loss_rel"] <= 1e-5 and acc["gradient"]["pass"])
-    del tr0
+    # settle the clocks before each timed run: steps of the throwaway trainer
+    # (learning rate 0) for WARM_S
+    def settle():
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < WARM_S:
+            for _ in range(20):
+                tr0.step()
+            torch.cuda.synchronize()
+
+    settle()
     trf = FusedTrainer(xd, orders, orders, L, h0)
     fused_ms, fused_loss = run(trf, steps)
     h_fused = trf.coeffs.cpu().numpy()
     del trf
+    settle()
     stage_ms, stage_loss = run(FusedTrainer(xd, orders, orders, L, h0, fused_transmitter=False), 50)
+    settle()
     auto_ms, auto_loss = run(AutogradTrainer(xd, orders, orders, L, h0), plain_steps)
+    settle()
     plain_ms, plain_loss = run(PlainTrainer(xd, orders, orders, L, h0), plain_steps)
+    del tr0
     k = min(plain_steps, steps)
     agree = float(np.max(np.abs(np.array(plain_loss[:k]) - np.array(fused_loss[:k])) /
                          np.array(fused_loss[:k])))
