@@ -698,7 +698,7 @@ def _learn_roofline(samples, ms, orders, L):
             "valu_tflops": round(samples * (fwd + bwd) / t / 1e12, 2),
             "valu_frac_nonpacked": round(samples * (fwd + bwd) / t / 1e12 / VALU_FP32_NONPACKED_TFLOPS, 4),
             "hbm_frac": round(samples * nbytes / t / 1e9 / HBM_PEAK_GBS, 4),
-            "note": "the whole step (four launches) against the non-packed FP32 VALU peak at 2.4 GHz and HBM peak"}
+            "note": "the whole step (three launches) against the non-packed FP32 VALU peak at 2.4 GHz and HBM peak"}
 
 
 def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):

@@ -292,8 +292,9 @@ dpd_status dpd_cascade_backward(const dpd_plan *A, const dpd_plan *B, void *stre
 
 /* dpd_transmit_loss_grad -- the forward pass of the learning step in one
  * kernel: z = D(x) (Eq. 1 with predistorter plan P and, when coeffs_dev is not
- * NULL, the K complex64 device coefficients coeffs_dev, precombined into P's
- * second table as in dpd_apply_coeffs), then u = A(z), y = B(u) and the loss
+ * NULL, the K complex64 device coefficients coeffs_dev, which the kernel
+ * precombines itself with the arithmetic of dpd_apply_coeffs' table; the
+ * plan's tables are not written), then u = A(z), y = B(u) and the loss
  * E and dE/dy of dpd_cascade_loss_grad (rows of x, z, grad_y at stride ld).
  * z is written for the cascade's adjoint (dpd_cascade_backward); z and grad_y
  * are bitwise those of dpd_apply_coeffs followed by dpd_cascade_loss_grad,
@@ -333,7 +334,7 @@ dpd_status dpd_transmit_backward(const dpd_plan *P, const dpd_plan *A, const dpd
                                  void *grad_coeffs, int64_t rows, int64_t n, int64_t ld, void *ws,
                                  size_t ws_bytes);
 
-/* dpd_learn_step -- one whole coefficient-learning step in one call (four
+/* dpd_learn_step -- one whole coefficient-learning step in one call (three
  * launches): the one-pass forward of dpd_transmit_loss_grad with the
  * coefficients coeffs_dev, the one-pass backward of dpd_transmit_backward,
  * then one launch that finalises the loss and the gradient (FP64, as those

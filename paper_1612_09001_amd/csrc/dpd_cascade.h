@@ -189,11 +189,12 @@ dpd_status check_transmit_forward(const dpd_plan *P, const dpd_plan *A, const dp
                                   float scale);
 
 // The one-pass forward of the learning step (dpd_transmit.hip): launches it
-// with table M and loss partials into `partials`; *nblk receives the number
-// of partials written.  Arguments already validated.
+// with the plan's coefficients, or with the K device coefficients coeffs_dev
+// (each block precombines them itself), loss partials into `partials`; *nblk
+// receives the number of partials written.  Arguments already validated.
 hipError_t launch_transmit_forward(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, hipStream_t hs,
-                                   const float *M, const void *x, void *z, void *grad_y, int64_t rows, int64_t n,
-                                   int64_t ld, float scale, float *partials, int *nblk);
+                                   const void *coeffs_dev, const void *x, void *z, void *grad_y, int64_t rows,
+                                   int64_t n, int64_t ld, float scale, float *partials, int *nblk);
 hipError_t launch_bwd_finalize(const float *partials, int nblk, const CoefMap &map, float2 *grad_coeffs,
                                hipStream_t st);
 

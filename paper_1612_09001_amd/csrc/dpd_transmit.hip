@@ -14,6 +14,10 @@
 // the predistorter's filter, stage A, stage B, the loss and dE/dy -- is the
 // same arithmetic, in the same order, as dpd_apply_coeffs followed by
 // dpd_cascade_loss_grad, so z and dE/dy are bitwise those of the two calls.
+// Given device coefficients, every block precombines the predistorter's table
+// itself into LDS (no table launch); a table of up to 96 floats then sits in
+// VGPRs, a larger one keeps its top Horner level in VGPRs and its lower levels
+// in LDS, read tap by tap.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,7 +39,9 @@ constexpr int kTxMaxNI = 5;              // predistorter: orders up to 9
 constexpr int kTxMaxL = kSpecL;          // predistorter: up to 8 taps
 
 struct TxParams {
-    const float *M;          // predistorter table
+    const float *M;          // predistorter table (used when raw is null)
+    const float2 *raw;       // or the K raw coefficients, precombined by every block
+    CoefMap map;
     const float *A, *B;      // transmitter stages
     const float2 *x;         // rows x n at stride ld
     float2 *z, *gy;          // outputs, same layout
@@ -44,6 +50,80 @@ struct TxParams {
     float *partials;         // one loss partial per block
     int vec;                 // rows start 16-byte aligned: whole octets use 16-byte accesses
 };
+
+// Entry e of the predistorter's precombined table (4 L NI matrix floats, then
+// c): read from the plan's table, or formed from the raw coefficients with
+// the arithmetic of the table kernel (hr+gr, gi-hi, hi+gi, hr-gr), so both give
+// the same bits.
+__device__ __forceinline__ float tx_table_entry(const TxParams &p, int e)
+{
+    if (p.raw == nullptr) return p.M[e];
+    const int L = p.map.L, NI = p.map.NI;
+    if (e >= 4 * L * NI) {
+        const float2 c = p.raw[(p.map.n_main + p.map.n_conj) * L];
+        return e == 4 * L * NI ? c.x : c.y;
+    }
+    const int k = e / (4 * NI), r = e - k * 4 * NI, j = r >> 2, q = r & 3;
+    float2 h = make_float2(0.f, 0.f), g = make_float2(0.f, 0.f);
+    if (p.map.main_idx[j] >= 0) h = p.raw[p.map.main_idx[j] * L + k];
+    if (p.map.conj_idx[j] >= 0) g = p.raw[(p.map.n_main + p.map.conj_idx[j]) * L + k];
+    return q == 0 ? h.x + g.x : q == 1 ? g.y - h.y : q == 2 ? h.y + g.y : h.x - g.x;
+}
+
+// The predistorter's filter for tables too large for registers: the top
+// Horner level of every tap in VGPRs (`top`), the lower levels of each tap
+// read from the LDS copy of the table just before the tap is used, the
+// arithmetic in the order of fir_outputs (the same bits).
+template <int NI, int L, int S>
+__device__ __forceinline__ void tx_fir_lds(const float (&a)[S + L - 1], const float (&b)[S + L - 1],
+                                           const float (&s)[S + L - 1], const float (&top)[4 * L],
+                                           const float *CS, float (&zr)[S], float (&zi)[S])
+{
+    constexpr int T = 4 * (NI - 1);
+    // An opaque zero keeps the table reads inside the caller's chunk loop:
+    // hoisted, every tap's lower levels would hold registers for the whole
+    // kernel.
+    int zo = 0;
+    asm volatile("" : "+v"(zo));
+    CS += zo;
+    const float2 c0 = *reinterpret_cast<const float2 *>(CS + 4 * L * NI);
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        zr[i] = c0.x;
+        zi[i] = c0.y;
+    }
+#pragma unroll
+    for (int k = 0; k < L; ++k) {
+        float c[T > 0 ? T : 1];
+        const float4 *ck = reinterpret_cast<const float4 *>(CS + 4 * NI * k);
+#pragma unroll
+        for (int j = 0; j < NI - 1; ++j) {
+            const float4 u = ck[j];
+            c[4 * j + 0] = u.x;
+            c[4 * j + 1] = u.y;
+            c[4 * j + 2] = u.z;
+            c[4 * j + 3] = u.w;
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const int w = i + (L - 1) - k;
+            float w00 = top[4 * k + 0], w01 = top[4 * k + 1];
+            float w10 = top[4 * k + 2], w11 = top[4 * k + 3];
+#pragma unroll
+            for (int j = NI - 2; j >= 0; --j) {
+                w00 = __builtin_fmaf(w00, s[w], c[4 * j + 0]);
+                w01 = __builtin_fmaf(w01, s[w], c[4 * j + 1]);
+                w10 = __builtin_fmaf(w10, s[w], c[4 * j + 2]);
+                w11 = __builtin_fmaf(w11, s[w], c[4 * j + 3]);
+            }
+            zr[i] = __builtin_fmaf(w00, a[w], zr[i]);
+            zr[i] = __builtin_fmaf(w01, b[w], zr[i]);
+            zi[i] = __builtin_fmaf(w10, a[w], zi[i]);
+            zi[i] = __builtin_fmaf(w11, b[w], zi[i]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
 
 template <int NI, int L>
 __global__ void __launch_bounds__(kBlock) transmit_fwd_kernel(TxParams p)
@@ -55,35 +135,36 @@ __global__ void __launch_bounds__(kBlock) transmit_fwd_kernel(TxParams p)
     constexpr int NC = 4 * L * NI + 2;
     constexpr bool REG = NC <= kRegCoefMax;
     constexpr int NB = 4 * LB * NIB + 2;     // stage-B table floats
-    constexpr int NV = REG ? NC : 4 * L;     // predistorter floats held in registers
     __shared__ float red[kBlock];
-    __shared__ float tab[NV + NB + 6];
+    __shared__ __align__(16) float mtab[NC + 2];
+    __shared__ float tab[NB + 6];
 
-    // Tables through LDS into registers (per-lane values: they stay in VGPRs
-    // and leave the scalar registers to the predistorter's scalar operands).
-    // Stage A is memoryless with one power level: u = c + M0 z.
+    // The predistorter's table into LDS (small tables then into VGPRs; larger
+    // ones are read tap by tap from LDS), the stage tables through LDS into
+    // VGPRs.  Stage A is memoryless with one power level: u = c + M0 z.
     const int tid = threadIdx.x;
-    if (tid < NV)
-        tab[tid] = REG ? p.M[tid] : p.M[(tid >> 2) * 4 * NI + 4 * (NI - 1) + (tid & 3)];
-    else if (tid < NV + NB)
-        tab[tid] = p.B[tid - NV];
-    else if (tid < NV + NB + 6)
-        tab[tid] = p.A[tid - NV - NB];
+    if (tid < NC)
+        mtab[tid] = tx_table_entry(p, tid);
+    else if (tid < NC + NB)
+        tab[tid - NC] = p.B[tid - NC];
+    else if (tid < NC + NB + 6)
+        tab[tid - NC] = p.A[tid - NC - NB];
     __syncthreads();
     float coef[REG ? NC : 1], top[REG ? 1 : 4 * L];
     if constexpr (REG) {
 #pragma unroll
-        for (int e = 0; e < NC; ++e) coef[e] = tab[e];
+        for (int e = 0; e < NC; ++e) coef[e] = mtab[e];
     } else {
 #pragma unroll
-        for (int e = 0; e < 4 * L; ++e) top[e] = tab[e];
+        for (int k = 0; k < L; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) top[4 * k + q] = mtab[4 * NI * k + 4 * (NI - 1) + q];
     }
-    const cfloat *Mc = as_const(p.M);
     float tb[NB], ta[6];
 #pragma unroll
-    for (int e = 0; e < NB; ++e) tb[e] = tab[NV + e];
+    for (int e = 0; e < NB; ++e) tb[e] = tab[e];
 #pragma unroll
-    for (int e = 0; e < 6; ++e) ta[e] = tab[NV + NB + e];
+    for (int e = 0; e < 6; ++e) ta[e] = tab[NB + e];
 
     float acc = 0.f;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
@@ -127,7 +208,7 @@ __global__ void __launch_bounds__(kBlock) transmit_fwd_kernel(TxParams p)
         if constexpr (REG)
             fir_outputs_reg<NI, L, ZW>(a, b, s, coef, zr, zi);
         else
-            fir_outputs<NI, L, ZW>(a, b, s, top, Mc, zr, zi);
+            tx_fir_lds<NI, L, ZW>(a, b, s, top, mtab, zr, zi);
         // u = A(z); zero before the row start (stage B's zero history)
         float2 u[ZW];
         float su[ZW];
@@ -219,35 +300,39 @@ __global__ void __launch_bounds__(kBlock) transmit_stream_kernel(TxParams p)
     constexpr int NC = 4 * L * NI + 2;
     constexpr bool REG = NC <= kRegCoefMax;
     constexpr int NB = 4 * LB * NIB + 2;
-    constexpr int NVT = REG ? NC : 4 * L;
-    __shared__ float tab[NVT + NB + 6];
+    __shared__ __align__(16) float mtab[NC + 2];
+    __shared__ float tab[REG ? NB + 6 : 1];
     __shared__ __align__(16) float2 xs[WAVES][PL::SLOTS];
     __shared__ __align__(16) float ss[WAVES][PL::SLOTS];
     __shared__ float red[WAVES];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    if (tid < NVT)
-        tab[tid] = REG ? p.M[tid] : p.M[(tid >> 2) * 4 * NI + 4 * (NI - 1) + (tid & 3)];
-    else if (tid < NVT + NB)
-        tab[tid] = p.B[tid - NVT];
-    else if (tid < NVT + NB + 6)
-        tab[tid] = p.A[tid - NVT - NB];
+    if (tid < NC)
+        mtab[tid] = tx_table_entry(p, tid);
+    else if (REG && tid < NC + NB)
+        tab[tid - NC] = p.B[tid - NC];
+    else if (REG && tid < NC + NB + 6)
+        tab[tid - NC] = p.A[tid - NC - NB];
     __syncthreads();
     float coef[REG ? NC : 1], top[REG ? 1 : 4 * L];
     if constexpr (REG) {
 #pragma unroll
-        for (int e = 0; e < NC; ++e) coef[e] = tab[e];
+        for (int e = 0; e < NC; ++e) coef[e] = mtab[e];
     } else {
 #pragma unroll
-        for (int e = 0; e < 4 * L; ++e) top[e] = tab[e];
+        for (int k = 0; k < L; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) top[4 * k + q] = mtab[4 * NI * k + 4 * (NI - 1) + q];
     }
-    const cfloat *Mc = as_const(p.M);
+    // the stage tables: per-lane copies through LDS beside a register-resident
+    // predistorter table; wave-uniform (scalar) operands beside an LDS-resident
+    // one, whose lower levels leave the scalar registers free
     float tb[NB], ta[6];
 #pragma unroll
-    for (int e = 0; e < NB; ++e) tb[e] = tab[NVT + e];
+    for (int e = 0; e < NB; ++e) tb[e] = REG ? tab[e] : p.B[e];
 #pragma unroll
-    for (int e = 0; e < 6; ++e) ta[e] = tab[NVT + NB + e];
+    for (int e = 0; e < 6; ++e) ta[e] = REG ? tab[NB + e] : p.A[e];
 
     float2 *X = xs[wv];
     float *SX = ss[wv];
@@ -314,7 +399,7 @@ __global__ void __launch_bounds__(kBlock) transmit_stream_kernel(TxParams p)
             if constexpr (REG)
                 fir_outputs_reg<NI, L, 1>(a, b, sv, coef, zr1, zi1);
             else
-                fir_outputs<NI, L, 1>(a, b, sv, top, Mc, zr1, zi1);
+                tx_fir_lds<NI, L, 1>(a, b, sv, top, mtab, zr1, zi1);
             cz[0] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zr1[0]), 0));
             cz[1] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zi1[0]), 0));
             cz[2] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(zr1[0]), 1));
@@ -358,7 +443,7 @@ __global__ void __launch_bounds__(kBlock) transmit_stream_kernel(TxParams p)
         if constexpr (REG)
             fir_outputs_reg<NI, L, S>(a, b, sw, coef, zr, zi);
         else
-            fir_outputs<NI, L, S>(a, b, sw, top, Mc, zr, zi);
+            tx_fir_lds<NI, L, S>(a, b, sw, top, mtab, zr, zi);
         // z at the two samples before this lane's: lane l - 1, or the carry
         float zh[4];
         zh[0] = shift_up(zr[S - 2], cz[0]);
@@ -512,14 +597,16 @@ static int tx_occupancy(int NI, int L, int which, const void *kern)
 }
 
 hipError_t launch_transmit_forward(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, hipStream_t hs,
-                                   const float *M, const void *x, void *z, void *grad_y, int64_t rows, int64_t n,
-                                   int64_t ld, float scale, float *partials, int *nblk)
+                                   const void *coeffs_dev, const void *x, void *z, void *grad_y, int64_t rows,
+                                   int64_t n, int64_t ld, float scale, float *partials, int *nblk)
 {
     *nblk = 0;
     const int64_t N = rows * n;
     if (N == 0) return hipSuccess;
     TxParams p;
-    p.M = M;
+    p.M = P->d_table;
+    p.raw = (const float2 *)coeffs_dev;
+    p.map = P->map;
     p.A = A->d_table;
     p.B = B->d_table;
     p.x = (const float2 *)x;
@@ -594,14 +681,9 @@ DPD_EXPORT dpd_status dpd_transmit_loss_grad(dpd_plan *P, const dpd_plan *A, con
     if (coeffs_dev != nullptr && (uintptr_t)coeffs_dev % 8 != 0) return DPD_EINVAL;
     const int64_t N = rows * n;
     const hipStream_t hs = (hipStream_t)stream;
-    const float *M = P->d_table;
-    if (coeffs_dev != nullptr) {
-        hipError_t e = launch_prep(P->map, coeffs_dev, P->d_table_call, hs);
-        if (e != hipSuccess) return hip_fail(e);
-        M = P->d_table_call;
-    }
     int nblk = 0;
-    hipError_t e = launch_transmit_forward(P, A, B, hs, M, x, z, grad_y, rows, n, ld, scale, (float *)ws, &nblk);
+    hipError_t e =
+        launch_transmit_forward(P, A, B, hs, coeffs_dev, x, z, grad_y, rows, n, ld, scale, (float *)ws, &nblk);
     if (e != hipSuccess) return hip_fail(e);
     if (loss_dev != nullptr) {
         e = launch_loss_finalize((const float *)ws, nblk, N > 0 ? 1.0 / (double)N : 0.0, loss_dev, hs);

@@ -467,12 +467,10 @@ DPD_EXPORT dpd_status dpd_learn_step(dpd_plan *P, const dpd_plan *A, const dpd_p
     if (!tb_shapes_ok(P, A, B, x, z, grad_y, nullptr, n, rs)) return DPD_EUNSUPPORTED;
     const hipStream_t hs = (hipStream_t)stream;
     const int64_t N = rows * n;
-    hipError_t e = launch_prep(P->map, coeffs_dev, P->d_table_call, hs);
-    if (e != hipSuccess) return hip_fail(e);
     float *lp = (float *)ws;
     float *dc = (float *)((char *)ws + learn_loss_bytes());
     int nloss = 0, nblk = 0;
-    e = launch_transmit_forward(P, A, B, hs, P->d_table_call, x, z, grad_y, rows, n, ld, scale, lp, &nloss);
+    hipError_t e = launch_transmit_forward(P, A, B, hs, coeffs_dev, x, z, grad_y, rows, n, ld, scale, lp, &nloss);
     if (e != hipSuccess) return hip_fail(e);
     e = launch_tb(P, A, B, hs, x, z, grad_y, nullptr, dc, rows, n, rs, &nblk);
     if (e != hipSuccess) return hip_fail(e);

@@ -2,10 +2,10 @@
 
 ``FusedTrainer.step()`` runs one full-batch gradient step entirely in libdpd
 kernels, on buffers allocated once.  With rows of whole 256-sample chunks it
-is one library call, ``dpd_learn_step`` (four launches):
+is one library call, ``dpd_learn_step`` (three launches):
 
-  table                      the predistorter's coefficients precombined
-  z, E, dE/dy                the predistorter, the synthetic transmitter
+  z, E, dE/dy                the predistorter (its table precombined from the
+                             device coefficients by every block), the synthetic transmitter
                              u = IQ(z), y = PA(u) (pa.py) and the loss
                              E = mean |y/G - x|^2 with its gradient in one
                              pass (u and y never stored, z written once)
