@@ -109,6 +109,24 @@ def test_config5_training_and_resume(torch):
     assert torch.equal(c.coeffs, a.coeffs)
 
 
+def test_config5_gradient_full_size_against_fp64_chain(torch, orc):
+    """The learning workload at its full size (64 x 2^18, one dpd_learn_step
+    call): loss and every coefficient-gradient entry at coefficients away
+    from the optimum against the FP64 chain over all 64 rows."""
+    import oracle.pa as opa
+    from paper_1612_09001_amd.train import FusedTrainer
+
+    x, xd = _data(torch, 64, 1 << 18, cid=9)
+    h = signals.aph_coeffs(*ORDERS, L, config_id=52)
+    h[0] += 1.0
+    tr = FusedTrainer(xd, *ORDERS, L, h, lr=0.0)
+    assert tr.one_call
+    loss = float(tr.step().item())
+    E, g = opa.chain_loss_and_gradient(orc, x, ORDERS, L, h)
+    assert abs(loss - E) <= 1e-5 * E, (loss, E)
+    assert_dcoef(tr.gc.cpu().numpy(), g, "chain gradient, 64 x 2^18", entry_max=1e-4, rel_max=1e-4)
+
+
 @pytest.mark.parametrize("n,off", [(100003, 0), (100003, 1), (1, 0), (2049, 1)])
 def test_loss_grad_against_fp64(torch, n, off):
     """dpd_loss_grad on 16-byte aligned buffers (two samples per access) and on
