@@ -141,35 +141,43 @@ def _timed(fn):
     return r, time.perf_counter() - t0
 
 
-def cpu_baseline(x_host, z_gpu, mo, co, L, h):
-    """FP64 oracle on the host cores over the whole headline workload (median
-    of 3); also gates the GPU output against it."""
-    orc = _oracle()
+CPU_BUDGET_S = 10.0   # host time spent timing the oracle on each thread count
+
+
+def _repeat_timed(fn, budget_s, min_runs=3):
+    """Runs fn until `budget_s` seconds (and at least min_runs runs) have
+    passed; returns the median run time and the number of runs."""
     times = []
-    z = None
-    for _ in range(3):
+    t_all = time.perf_counter()
+    while len(times) < min_runs or time.perf_counter() - t_all < budget_s:
         t = time.perf_counter()
-        z = orc.forward(x_host, mo, co, L, h)
+        fn()
         times.append(time.perf_counter() - t)
-    t = float(np.median(times))
+    return float(np.median(times)), len(times)
+
+
+def cpu_baseline(x_host, z_gpu, mo, co, L, h):
+    """FP64 oracle on the host cores over the whole headline workload, repeated
+    for about CPU_BUDGET_S seconds (median run); also gates the GPU output
+    against it."""
+    orc = _oracle()
+    z = orc.forward(x_host, mo, co, L, h)
+    t, runs = _repeat_timed(lambda: orc.forward(x_host, mo, co, L, h), CPU_BUDGET_S)
     n = x_host.size
     acc = gate(z_gpu, z)
     threads = orc.threads()
     # the same oracle on one thread, over the first 2^21 samples
     m = min(n, 1 << 21)
     orc.set_threads(1)
-    t1 = []
-    for _ in range(3):
-        t0 = time.perf_counter()
-        orc.forward(x_host[:m], mo, co, L, h)
-        t1.append(time.perf_counter() - t0)
+    t1, runs1 = _repeat_timed(lambda: orc.forward(x_host[:m], mo, co, L, h), CPU_BUDGET_S)
     orc.set_threads(threads)
     base = {"value": round(n / t / 1e6, 3), "unit": "Msamples/s", "cores": threads,
             "kind": "oracle",
             "sample": "whole headline workload: %d samples through the FP64 C oracle "
-                      "(gcc -O2, OpenMP), median of 3" % n,
-            "single_thread_value": round(m / float(np.median(t1)) / 1e6, 3),
-            "single_thread_sample": "first %d samples of the same workload, one thread, median of 3" % m,
+                      "(gcc -O2, OpenMP), median of %d runs over about %g s" % (n, runs, CPU_BUDGET_S),
+            "single_thread_value": round(m / t1 / 1e6, 3),
+            "single_thread_sample": "first %d samples of the same workload, one thread, median of %d runs over "
+                                    "about %g s" % (m, runs1, CPU_BUDGET_S),
             "cpu_model": _cpu_model()}
     return base, acc
 
