@@ -67,6 +67,12 @@ struct BatchParams {
     int64_t n_full;
     int64_t n_chunks;
     const float *tables;
+    // Full chunks [0, n_heavy) go to the waves of the blocks in the dispatch
+    // slots not in light_mask, [n_heavy, n_full) to those in it (slot of a
+    // block: blockIdx / ncu).  light_mask 0: every wave walks the whole list.
+    int64_t n_heavy;
+    int32_t ncu;
+    int32_t light_mask;
 };
 
 // Wave-uniform view of a descriptor (scalar registers).
@@ -336,9 +342,33 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(BatchParams bp)
     float2 *X = xs[wv];
     float *SX = ss[wv];
     float *CS = cs[wv];
-    const int64_t nw = (int64_t)gridDim.x * WAVES;
-    const int64_t gw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * WAVES + wv;
-    const int64_t nf = bp.n_full;
+    int64_t nw = (int64_t)gridDim.x * WAVES;
+    int64_t gw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * WAVES + wv;
+    int64_t nf = bp.n_full, base = 0;
+    // Heavy and light chunks side by side: the dispatcher fills one block slot
+    // of every CU before the next, so the blocks of one slot share no SIMD
+    // with each other and the waves of a light-slot block run beside waves of
+    // heavy-slot blocks -- VALU-bound and memory-bound chunks on one SIMD at
+    // once.  Each group walks its own part of the cost-sorted list, wave-
+    // strided in its own rank order (XCD-contiguous, as xcd_remap).  Any
+    // placement of the blocks still covers every chunk exactly once.
+    if (bp.light_mask != 0) {
+        const int slot = blockIdx.x / bp.ncu, cu = blockIdx.x - slot * bp.ncu;
+        const int nslots = gridDim.x / bp.ncu;
+        const bool light = (bp.light_mask >> slot) & 1;
+        int r = 0, cnt = 0;
+        for (int s2 = 0; s2 < nslots; ++s2) {
+            const bool l2 = (bp.light_mask >> s2) & 1;
+            if (l2 == light) {
+                if (s2 < slot) ++r;
+                ++cnt;
+            }
+        }
+        gw = ((int64_t)r * bp.ncu + xcd_remap(cu, bp.ncu)) * WAVES + wv;
+        nw = (int64_t)cnt * bp.ncu * WAVES;
+        base = light ? bp.n_heavy : 0;
+        nf = (light ? bp.n_full : bp.n_heavy) - base;
+    }
 
     // full chunks gw, gw + nw, ...: while one staged chunk is filtered, the
     // next chunk's loads are in flight (its descriptor was fetched one chunk
@@ -347,7 +377,7 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(BatchParams bp)
     // last chunk the loads read the idle entry, whose samples stay in the L2.
     if (gw < nf) {
         const int64_t left = (nf - 1 - gw) / nw + 1;
-        const auto idx = [&](int64_t i) { return i < left ? gw + i * nw : bp.n_chunks; };
+        const auto idx = [&](int64_t i) { return i < left ? base + gw + i * nw : bp.n_chunks; };
         BatchRegs<S> R;
         BatchDesc Dc = batch_desc_read(batch_desc_load(bp.chunks, idx(0), lane));
         uint32_t dn = batch_desc_load(bp.chunks, idx(1), lane);

@@ -138,10 +138,13 @@ def config4(torch, mods, orc):
 
 
 # the library's default launch shape and the benchmark's autotuned ones
+# (whole slots of blocks per CU: the heavy/light split with two, three and
+# more slots)
 @pytest.mark.parametrize("tune", [None, {"samples_per_thread": 8, "grid_mult": 16},
                                   {"samples_per_thread": 8, "grid_mult": 4},
+                                  {"samples_per_thread": 8, "grid_mult": 2},
                                   {"samples_per_thread": 4, "grid_mult": 8}],
-                         ids=["default", "S8_g16", "S8_g4", "S4_g8"])
+                         ids=["default", "S8_g16", "S8_g4", "S8_g2", "S4_g8"])
 def test_config4_every_stream_full(torch, mods, config4, tune):
     """256 streams, lengths U[2^14, 2^20], P_max in {5,7,9}, L in {2..8}: every
     output of every stream against the FP64 oracle."""
