@@ -90,15 +90,22 @@ __global__ void __launch_bounds__(kBlock) bwd_dx_generic(BwdParams p, int NI, in
 // contiguous range of the flattened rows); one partial per (block, entry).
 __global__ void __launch_bounds__(kBlock) bwd_dc_generic(BwdParams p, int NI, int L)
 {
-    __shared__ float red[kBlock];
+    __shared__ double red[kBlock];
     const int E = 4 * L * NI + 2;
     const int64_t total = p.rows * p.n;
     const int64_t per = (total + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)blockIdx.x * per;
     const int64_t hi = lo + per < total ? lo + per : total;
+    // FP32 sums over at most 64 samples per thread, then FP64
     float acc[kGroup];
-    for (int q = 0; q < kGroup; ++q) acc[q] = 0.f;
+    double accd[kGroup];
+    for (int q = 0; q < kGroup; ++q) acc[q] = 0.f, accd[q] = 0.0;
+    int cnt = 0;
     for (int64_t idx = lo + threadIdx.x; idx < hi; idx += kBlock) {
+        if (++cnt == 64) {
+            for (int q = 0; q < kGroup; ++q) accd[q] += acc[q], acc[q] = 0.f;
+            cnt = 0;
+        }
         const int64_t row = idx / p.n, m = idx - row * p.n;
         const float2 v = p.x[row * p.ld + m];
         const float s = __builtin_fmaf(v.x, v.x, v.y * v.y);
@@ -123,13 +130,13 @@ __global__ void __launch_bounds__(kBlock) bwd_dc_generic(BwdParams p, int NI, in
     for (int q = 0; q < kGroup; ++q) {
         const int e = blockIdx.y * kGroup + q;
         if (e >= E) break;
-        red[threadIdx.x] = acc[q];
+        red[threadIdx.x] = accd[q] + (double)acc[q];
         __syncthreads();
         for (int w = kBlock / 2; w > 0; w >>= 1) {
             if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
-        if (threadIdx.x == 0) p.partials[(int64_t)blockIdx.x * E + e] = red[0];
+        if (threadIdx.x == 0) p.partials[(int64_t)blockIdx.x * E + e] = (float)red[0];
         __syncthreads();
     }
 }

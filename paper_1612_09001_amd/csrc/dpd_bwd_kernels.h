@@ -15,9 +15,10 @@
 // stacking happens in the FP64 finalisation kernel.
 //
 // Reduction of the coefficient gradient is deterministic: each lane sums its
-// own samples in a fixed order (FP32), the wave and the block reduce in a fixed
-// tree, one FP32 partial per block goes to the workspace, and a single block
-// sums the partials in FP64 in block order.
+// own samples in a fixed order (FP32, at most kBwdFlush chunks at a time), the
+// wave reduces those sums in a fixed tree into its FP64 totals, the block adds
+// its waves' totals in order, one partial per block goes to the workspace, and
+// a single block sums the partials in FP64 in block order.
 #pragma once
 
 #include "dpd_fwd_kernels.h"
@@ -52,19 +53,9 @@ void register_bwd_ni7(BwdTable &);
 void register_bwd_ni8(BwdTable &);
 
 constexpr int kBwdS = 4;   // consecutive samples per lane
-
-// The wave totals of E per-lane accumulators into out[0..E) (LDS): every
-// accumulator reduced in place, then lane 63 stores them all.
-template <int E>
-__device__ __forceinline__ void store_wave_totals(float (&acc)[E], float *out, int lane)
-{
-#pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = wave_sum_to_lane63(acc[e]);
-    if (lane == 63) {
-#pragma unroll
-        for (int e = 0; e < E; ++e) out[e] = acc[e];
-    }
-}
+// Chunks a lane's FP32 coefficient-gradient sums cover before they are added
+// to the wave's FP64 totals (a power of two): 32 chunks = 128 samples per lane.
+constexpr int kBwdFlush = 32;
 
 // FP64 sums of table entry q's four coefficient-gradient partials (two for
 // q = L NI, the c entry) over nblk blocks: each thread its strided share of
@@ -162,7 +153,7 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
     __shared__ __align__(16) float2 gs[WAVES][GSLOTS];
     __shared__ __align__(16) float2 xsh[WAVES][XSLOTS];
     __shared__ __align__(16) float mt[NM];
-    __shared__ float red[DC ? WAVES * E : 1];
+    __shared__ double red[DC ? WAVES * E : 1];   // per-wave FP64 totals of the coefficient gradient
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -177,6 +168,21 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
     float acc[DC ? E : 1];
 #pragma unroll
     for (int e = 0; e < (DC ? E : 1); ++e) acc[e] = 0.f;
+    // The per-lane FP32 sums cover at most kBwdFlush chunks: then they are
+    // summed over the wave and added to the wave's FP64 totals (entry
+    // 64 g + l in lane l of tot[g]), so the rounding error does not grow with
+    // the stream length.
+    constexpr int NGT = DC ? (E + 63) / 64 : 1;
+    double tot[NGT];
+#pragma unroll
+    for (int g = 0; g < NGT; ++g) tot[g] = 0.0;
+    auto flush = [&]() {
+        if constexpr (DC) {
+            wave_sums_into<E>(acc, tot, lane);
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e] = 0.f;
+        }
+    };
 
     struct Regs {
         float4 g[NV];
@@ -383,6 +389,7 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
             load_full(R, row, tix * C);
             compute(crow, ct0, BwdTag<true>{});
             stage(R, tix * C);
+            if ((i & (kBwdFlush - 1)) == kBwdFlush - 1) flush();
         }
         compute(row, tix * C, BwdTag<true>{});
     }
@@ -397,14 +404,17 @@ __global__ void __launch_bounds__(kBlock) bwd_kernel(BwdParams p)
     }
 
     if constexpr (DC) {
-        // wave -> block -> one FP32 partial per block, fixed order
-        store_wave_totals<E>(acc, red + wv * E, lane);
+        // wave FP64 totals -> block -> one FP32 partial per block, fixed order
+        flush();
+#pragma unroll
+        for (int g = 0; g < NGT; ++g)
+            if (64 * g + lane < E) red[wv * E + 64 * g + lane] = tot[g];
         __syncthreads();
         for (int e = tid; e < E; e += kBlock) {
-            float t = 0.f;
+            double t = 0.0;
 #pragma unroll
             for (int w = 0; w < WAVES; ++w) t += red[w * E + e];
-            p.partials[(int64_t)blockIdx.x * E + e] = t;
+            p.partials[(int64_t)blockIdx.x * E + e] = (float)t;
         }
     }
 }

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace dpd {
 
 // One DPP step of a lane reduction: x from the lane that CTRL selects (rows
@@ -41,6 +43,62 @@ __device__ __forceinline__ T wave_sum_to_lane63(T v)
     v += dpp_from<0x142, 0xa>(v);
     v += dpp_from<0x143, 0xc>(v);
     return v;
+}
+
+// N <= 64 per-lane values v[0..N) summed over the wave, transposed: lane l
+// returns the sum of v[l] over all 64 lanes (zero for l >= N); v is
+// overwritten.  Six butterfly stages; at the stage of lane stride o the
+// registers pair up (i, i + o) and each lane keeps the one its lane bit o
+// selects, adding its partner's copy of it, so every stage halves the
+// registers still live (at most 63 exchanges instead of N separate
+// reductions).  Fixed order: the same inputs give the same bits.
+template <int N>
+__device__ __forceinline__ float wave_transpose_sum(float (&v)[N], int lane)
+{
+    static_assert(N >= 1 && N <= 64, "one register per lane and group");
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < o && i < N; ++i) {
+            const float other = i + o < N ? v[i + o] : 0.f;
+            const float keep = up ? other : v[i];
+            const float send = up ? v[i] : other;
+            v[i] = keep + __shfl_xor(send, o);
+        }
+    }
+    return v[0];
+}
+
+// Calls f(std::integral_constant<int, G>) for G = 0 .. NG-1.
+template <int G, int NG>
+struct ForEachGroup {
+    template <class F>
+    __device__ __forceinline__ static void run(F &f)
+    {
+        f(std::integral_constant<int, G>{});
+        ForEachGroup<G + 1, NG>::run(f);
+    }
+};
+template <int NG>
+struct ForEachGroup<NG, NG> {
+    template <class F>
+    __device__ __forceinline__ static void run(F &)
+    {
+    }
+};
+
+// The wave sums of E per-lane accumulators added to FP64 totals held
+// transposed (entry 64 g + l in lane l of tot[g]); acc is consumed.
+template <int E>
+__device__ __forceinline__ void wave_sums_into(float (&acc)[E], double (&tot)[(E + 63) / 64], int lane)
+{
+    auto one = [&](auto gc) {
+        constexpr int g = decltype(gc)::value;
+        constexpr int n = E - 64 * g < 64 ? E - 64 * g : 64;
+        tot[g] += (double)wave_transpose_sum<n>(*reinterpret_cast<float(*)[n]>(&acc[64 * g]), lane);
+    };
+    ForEachGroup<0, (E + 63) / 64>::run(one);
 }
 
 }  // namespace dpd

@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(kBlock) transmit_bwd_kernel(TbParams p)
     __shared__ __align__(16) float2 ys[WAVES][YSLOTS];
     __shared__ __align__(16) float2 xsh[WAVES][XSLOTS];
     __shared__ __align__(16) float2 zsh[WAVES][XSLOTS];
-    __shared__ float red[WAVES * E];
+    __shared__ double red[WAVES * E];   // per-wave FP64 totals of the coefficient gradient
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -81,6 +81,18 @@ __global__ void __launch_bounds__(kBlock) transmit_bwd_kernel(TbParams p)
     float acc[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = 0.f;
+    // per-lane FP32 sums over at most kBwdFlush chunks, then into the wave's
+    // FP64 totals, entry 64 g + l in lane l of tot[g] (the rounding error does
+    // not grow with the batch size)
+    constexpr int NGT = (E + 63) / 64;
+    double tot[NGT];
+#pragma unroll
+    for (int g = 0; g < NGT; ++g) tot[g] = 0.0;
+    auto flush = [&]() {
+        wave_sums_into<E>(acc, tot, lane);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = 0.f;
+    };
 
     // G at sample m of a row from z and dE/dy (zero past the row end): the
     // arithmetic of dpd_cascade_backward
@@ -252,18 +264,22 @@ __global__ void __launch_bounds__(kBlock) transmit_bwd_kernel(TbParams p)
             compute(crow, ck * C, carry);
             if (ck == 0) carry = make_float2(0.f, 0.f);   // the chunk before ends a row
             stage(R);
+            if (((c_end - c_begin - left) & (kBwdFlush - 1)) == kBwdFlush - 1) flush();
         }
         compute(row, k * C, carry);
     }
 
-    // wave -> block -> one FP32 partial per block, fixed order
-    store_wave_totals<E>(acc, red + wv * E, lane);
+    // wave FP64 totals -> block -> one FP32 partial per block, fixed order
+    flush();
+#pragma unroll
+    for (int g = 0; g < NGT; ++g)
+        if (64 * g + lane < E) red[wv * E + 64 * g + lane] = tot[g];
     __syncthreads();
     for (int e = tid; e < E; e += kBlock) {
-        float t = 0.f;
+        double t = 0.0;
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) t += red[w * E + e];
-        p.partials[(int64_t)blockIdx.x * E + e] = t;
+        p.partials[(int64_t)blockIdx.x * E + e] = (float)t;
     }
 }
 

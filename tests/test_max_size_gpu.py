@@ -1,0 +1,99 @@
+"""A stream longer than 2^31 samples (64-bit indexing in every kernel): the
+forward and the backward of the headline basis at N = 2^31 + 2^20 + 777
+against the FP64 oracle.  The input and the output gradient repeat seeded
+blocks of P = 2^20 samples, so the oracle gets each sampled output from the
+L-sample window it depends on, and the whole coefficient gradient from three
+runs over one block: the first block (zero history), one later block (the
+block's own end as history, weighted by the number of such blocks) and the
+ragged end."""
+import numpy as np
+import pytest
+
+from metrics import assert_dcoef, assert_parity
+from paper_1612_09001_amd import signals
+
+pytestmark = pytest.mark.gpu
+
+P = 1 << 20
+N = (1 << 31) + P + 777
+MO = CO = [1, 3, 5, 7]
+L = 4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def dpd(torch):
+    from paper_1612_09001_amd import dpd as d
+
+    d.lib()
+    return d
+
+
+def _repeat(torch, block):
+    """The block repeated to N samples on the device (a contiguous view)."""
+    b = torch.from_numpy(np.ascontiguousarray(block, dtype=np.complex64)).cuda()
+    return b.repeat(N // P + 1)[:N]
+
+
+def _sample_indices():
+    rng = np.random.default_rng(5)
+    edges = [0, 1, 2, 3, P - 2, P - 1, P, P + 1, (1 << 31) - 1, 1 << 31, (1 << 31) + 1, N - 1]
+    near = np.concatenate([np.arange(e - 8, e + 8) for e in edges])
+    # chunk starts of the 512-sample forward and 256-sample backward walks past 2^31
+    chunks = (1 << 31) + np.arange(-4, 5) * 512
+    idx = np.concatenate([near, chunks, rng.integers(0, N, 4096)])
+    return np.unique(idx[(idx >= 0) & (idx < N)])
+
+
+def _windows(block, idx, back):
+    """Per index i the L samples the oracle needs, as one compact array:
+    x_{i-L+1..i} (zero before the stream start) when back is False, else
+    x_{i..i+L-1} (zero past the stream end)."""
+    off = np.arange(L) - (L - 1) if not back else np.arange(L)
+    pos = idx[:, None] + off[None, :]
+    w = block[np.mod(pos, P)]
+    w[(pos < 0) | (pos >= N)] = 0
+    return w.reshape(-1)
+
+
+def test_forward_past_2_31(torch, dpd, orc):
+    x_blk = signals.ofdm_16qam(P, config_id=2).astype(np.complex64)
+    h = signals.aph_coeffs(MO, CO, L, config_id=2)
+    x = _repeat(torch, x_blk)
+    z = dpd.Plan(MO, CO, L, h).apply(x)
+    idx = _sample_indices()
+    got = z[torch.from_numpy(idx).cuda()].cpu().numpy()
+    del z, x
+    ref = orc.forward_at(_windows(x_blk, idx, False), MO, CO, L, h, np.arange(idx.size) * L + L - 1)
+    assert_parity(got, ref, "forward at N = 2^31 + 2^20 + 777")
+
+
+def test_backward_past_2_31(torch, dpd, orc):
+    x_blk = signals.ofdm_16qam(P, config_id=2).astype(np.complex64)
+    g_blk = (signals.ofdm_16qam(P, config_id=12) * 1e-3).astype(np.complex64)
+    h = signals.aph_coeffs(MO, CO, L, config_id=2)
+    x, g = _repeat(torch, x_blk), _repeat(torch, g_blk)
+    gx, gc = dpd.Plan(MO, CO, L, h).backward(x, g)
+    idx = _sample_indices()
+    got = gx[torch.from_numpy(idx).cuda()].cpu().numpy()
+    gc = gc.cpu().numpy()
+    del gx, x, g
+    # dx_i depends on x_i and G_{i..i+L-1}: the first output of each window
+    rx, _ = orc.backward(_windows(x_blk, idx, True), MO, CO, L, h, _windows(g_blk, idx, True), want_dcoef=False)
+    assert_parity(got, rx[::L], "dx at N = 2^31 + 2^20 + 777")
+    # the coefficient gradient: first block + (full blocks - 1) later blocks + the ragged end
+    hist = x_blk[P - (L - 1):]
+    _, first = orc.backward(x_blk, MO, CO, L, h, g_blk, want_dx=False)
+    _, later = orc.backward(x_blk, MO, CO, L, h, g_blk, hist=hist, want_dx=False)
+    R = N % P
+    _, end = orc.backward(x_blk[:R], MO, CO, L, h, g_blk[:R], hist=hist, want_dx=False)
+    ref = first + (N // P - 1) * later + end
+    assert_dcoef(gc, ref, "dcoef at N = 2^31 + 2^20 + 777")
