@@ -12,6 +12,25 @@ namespace dpd {
 
 constexpr int kLossBlocks = 1024;   // loss partials (one per block of the loss kernels)
 
+// A thread's (or lane's) share of a loss sum: FP32 over at most kLossFlush
+// loop steps, then added to an FP64 total, so the rounding error does not grow
+// with the number of samples one thread sums.
+constexpr int kLossFlush = 32;
+struct LossSum {
+    float f = 0.f;
+    double d = 0.0;
+    int c = 0;
+    __device__ __forceinline__ void step_done()
+    {
+        if (++c == kLossFlush) {
+            d += (double)f;
+            f = 0.f;
+            c = 0;
+        }
+    }
+    __device__ __forceinline__ double total() const { return d + (double)f; }
+};
+
 constexpr int kCasTA = 4 * kMaxNI + 2;   // stage-A table floats held in registers (at most)
 
 // A(z) for one sample (memoryless: c + W(|z|^2) z, W by Horner over NIA

@@ -29,12 +29,12 @@ __global__ void __launch_bounds__(kBlock) loss_kernel(const float2 *__restrict__
                                                       int64_t n, float s, float gscale, float2 *__restrict__ gy,
                                                       float *__restrict__ partials, int vec)
 {
-    __shared__ float red[kBlock];
+    __shared__ double red[kBlock];
     constexpr int64_t CH = 2 * kBlock;
-    float acc = 0.f;
+    LossSum ls;
     const auto one = [&](float2 a, float2 b) {
         const float rr = __builtin_fmaf(s, a.x, -b.x), ri = __builtin_fmaf(s, a.y, -b.y);
-        acc = __builtin_fmaf(rr, rr, __builtin_fmaf(ri, ri, acc));
+        ls.f = __builtin_fmaf(rr, rr, __builtin_fmaf(ri, ri, ls.f));
         return make_float2(gscale * rr, gscale * ri);
     };
     for (int64_t c0 = (int64_t)blockIdx.x * CH; c0 < n; c0 += (int64_t)gridDim.x * CH) {
@@ -53,14 +53,15 @@ __global__ void __launch_bounds__(kBlock) loss_kernel(const float2 *__restrict__
                     if (gy != nullptr) gy[t + i] = g0;
                 }
         }
+        ls.step_done();
     }
-    red[threadIdx.x] = acc;
+    red[threadIdx.x] = ls.total();
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) partials[blockIdx.x] = (float)red[0];
 }
 
 // FP64 sum of the block partials: thread t takes partials t, t + 256, ... in
@@ -127,10 +128,10 @@ template <int NIB, int LB>
 __global__ void __launch_bounds__(kBlock) cascade_fwd_kernel(CasParams p)
 {
     constexpr int W = kCasQ + LB - 1;
-    __shared__ float red[kBlock];
+    __shared__ double red[kBlock];
     float ta[kCasTA], tb[4 * LB * NIB + 2];
     cas_tables<NIB, LB>(p, ta, tb);
-    float acc = 0.f;
+    LossSum ls;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t q0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     CasWalk wk(q0, stride, p.qpr);
@@ -196,7 +197,7 @@ __global__ void __launch_bounds__(kBlock) cascade_fwd_kernel(CasParams p)
             const bool in = m0 + i < p.n;
             const float rr = in ? __builtin_fmaf(p.scale, yr, -xv[i].x) : 0.f;
             const float ri = in ? __builtin_fmaf(p.scale, yi, -xv[i].y) : 0.f;
-            acc = __builtin_fmaf(rr, rr, __builtin_fmaf(ri, ri, acc));
+            ls.f = __builtin_fmaf(rr, rr, __builtin_fmaf(ri, ri, ls.f));
             g[i] = make_float2(p.gscale * rr, p.gscale * ri);
         }
         if (vec) {
@@ -207,14 +208,15 @@ __global__ void __launch_bounds__(kBlock) cascade_fwd_kernel(CasParams p)
             for (int i = 0; i < kCasQ; ++i)
                 if (m0 + i < p.n) gr[m0 + i] = g[i];
         }
+        ls.step_done();
     }
-    red[threadIdx.x] = acc;
+    red[threadIdx.x] = ls.total();
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) p.partials[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) p.partials[blockIdx.x] = (float)red[0];
 }
 
 // Backward: dE/dz = A'(z)^T B'(u)^T dE/dy with u = A(z) recomputed.

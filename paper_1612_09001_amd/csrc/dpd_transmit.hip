@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(kBlock) transmit_fwd_kernel(TxParams p)
     constexpr int NC = 4 * L * NI + 2;
     constexpr bool REG = NC <= kRegCoefMax;
     constexpr int NB = 4 * LB * NIB + 2;     // stage-B table floats
-    __shared__ float red[kBlock];
+    __shared__ double red[kBlock];
     __shared__ __align__(16) float mtab[NC + 2];
     __shared__ float tab[NB + 6];
 
@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(kBlock) transmit_fwd_kernel(TxParams p)
 #pragma unroll
     for (int e = 0; e < 6; ++e) ta[e] = tab[NB + e];
 
-    float acc = 0.f;
+    LossSum ls;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t q0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     CasWalk wk(q0, stride, p.qpr);
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(kBlock) transmit_fwd_kernel(TxParams p)
             const bool in = m0 + i < p.n;
             const float rr = in ? __builtin_fmaf(p.scale, yr, -a[XH + i]) : 0.f;
             const float ri = in ? __builtin_fmaf(p.scale, yi, -b[XH + i]) : 0.f;
-            acc = __builtin_fmaf(rr, rr, __builtin_fmaf(ri, ri, acc));
+            ls.f = __builtin_fmaf(rr, rr, __builtin_fmaf(ri, ri, ls.f));
             g[i] = make_float2(p.gscale * rr, p.gscale * ri);
         }
         if (vec) {
@@ -263,14 +263,15 @@ __global__ void __launch_bounds__(kBlock) transmit_fwd_kernel(TxParams p)
                     grow[m0 + i] = g[i];
                 }
         }
+        ls.step_done();
     }
-    red[threadIdx.x] = acc;
+    red[threadIdx.x] = ls.total();
     __syncthreads();
     for (int w = kBlock / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) p.partials[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) p.partials[blockIdx.x] = (float)red[0];
 }
 
 // lane l receives v of lane l - 1; lane 0 receives `first` (wave-uniform)
@@ -304,7 +305,7 @@ __global__ void __launch_bounds__(kBlock) transmit_stream_kernel(TxParams p)
     __shared__ float tab[REG ? NB + 6 : 1];
     __shared__ __align__(16) float2 xs[WAVES][PL::SLOTS];
     __shared__ __align__(16) float ss[WAVES][PL::SLOTS];
-    __shared__ float red[WAVES];
+    __shared__ double red[WAVES];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -344,7 +345,7 @@ __global__ void __launch_bounds__(kBlock) transmit_stream_kernel(TxParams p)
     const int64_t c_begin = gw * per < total ? gw * per : total;
     const int64_t c_end = c_begin + per < total ? c_begin + per : total;
     const int hl = HS > 0 ? (lane < HS ? lane : HS - 1) : 0;
-    float acc = 0.f;
+    LossSum ls;   // this lane's share, flushed to FP64 every kLossFlush chunks
 
     struct Cur {
         int64_t row, k;
@@ -490,7 +491,7 @@ __global__ void __launch_bounds__(kBlock) transmit_stream_kernel(TxParams p)
             }
             const float rr = __builtin_fmaf(p.scale, yr, -a[L - 1 + i]);
             const float ri = __builtin_fmaf(p.scale, yi, -b[L - 1 + i]);
-            acc = __builtin_fmaf(rr, rr, __builtin_fmaf(ri, ri, acc));
+            ls.f = __builtin_fmaf(rr, rr, __builtin_fmaf(ri, ri, ls.f));
             gr[i] = p.gscale * rr;
             gi[i] = p.gscale * ri;
         }
@@ -515,6 +516,7 @@ __global__ void __launch_bounds__(kBlock) transmit_stream_kernel(TxParams p)
                 __builtin_nontemporal_store(v, o4 + lane + 64 * i);
             }
         }
+        ls.step_done();
     };
 
     if (c_begin < c_end) {
@@ -542,16 +544,17 @@ __global__ void __launch_bounds__(kBlock) transmit_stream_kernel(TxParams p)
             step(A, cur);
         }
     }
-    // wave -> block -> one loss partial per block (fixed order)
+    // wave -> block -> one loss partial per block (fixed order, FP64)
+    double acc = ls.total();
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (lane == 0) red[wv] = acc;
     __syncthreads();
     if (tid == 0) {
-        float t = red[0];
+        double t = red[0];
 #pragma unroll
         for (int w = 1; w < WAVES; ++w) t += red[w];
-        p.partials[blockIdx.x] = t;
+        p.partials[blockIdx.x] = (float)t;
     }
 }
 

@@ -1,11 +1,14 @@
-"""A stream longer than 2^31 samples (64-bit indexing in every kernel): the
-forward and the backward of the headline basis at N = 2^31 + 2^20 + 777
-against the FP64 oracle.  The input and the output gradient repeat seeded
-blocks of P = 2^20 samples, so the oracle gets each sampled output from the
-L-sample window it depends on, and the whole coefficient gradient from three
-runs over one block: the first block (zero history), one later block (the
-block's own end as history, weighted by the number of such blocks) and the
-ragged end."""
+"""More than 2^31 samples in one call (64-bit indexing in every kernel, sums
+whose rounding error must not grow with the length): the forward and the
+backward of the headline basis on one stream of N = 2^31 + 2^20 + 777
+samples, and one learning step over 8193 rows of 2^18, against the FP64
+oracle.  The stream and its output gradient repeat seeded blocks of P = 2^20
+samples, so the oracle gets each sampled output from the L-sample window it
+depends on, and the whole coefficient gradient from three runs over one
+block: the first block (zero history), one later block (the block's own end
+as history, weighted by the number of such blocks) and the ragged end.  The
+learning rows are all the same seeded row, so the mean loss and its gradient
+are those of that row."""
 import numpy as np
 import pytest
 
@@ -97,3 +100,25 @@ def test_backward_past_2_31(torch, dpd, orc):
     _, end = orc.backward(x_blk[:R], MO, CO, L, h, g_blk[:R], hist=hist, want_dx=False)
     ref = first + (N // P - 1) * later + end
     assert_dcoef(gc, ref, "dcoef at N = 2^31 + 2^20 + 777")
+
+
+def test_learning_step_past_2_31(torch, orc):
+    """One dpd_learn_step over 8193 identical rows of 2^18 samples (2^31 + 2^18
+    in all): the loss and every coefficient-gradient entry against the FP64
+    chain over the one row, at coefficients away from the optimum."""
+    import oracle.pa as opa
+    from paper_1612_09001_amd.train import FusedTrainer
+
+    orders, Lt, n, rows = [1, 3, 5, 7], 6, 1 << 18, (1 << 13) + 1
+    row = signals.ofdm_16qam(n, config_id=9, stream_id=0)
+    xd = torch.from_numpy(row).cuda().reshape(1, n).repeat(rows, 1)
+    h = signals.aph_coeffs(orders, orders, Lt, config_id=52)
+    h[0] += 1.0
+    tr = FusedTrainer(xd, orders, orders, Lt, h, lr=0.0)
+    assert tr.one_call
+    loss = float(tr.step().item())
+    gc = tr.gc.cpu().numpy()
+    del tr, xd
+    E, g = opa.chain_loss_and_gradient(orc, row[None, :], (orders, orders), Lt, h)
+    assert abs(loss - E) <= 1e-5 * E, (loss, E)
+    assert_dcoef(gc, g, "chain gradient, 8193 x 2^18", entry_max=1e-4, rel_max=1e-4)
