@@ -178,7 +178,9 @@ dpd_status dpd_apply_hist(dpd_plan *plan, void *stream, const void *in, void *ou
  *                NULL to skip it
  *   ws, ws_bytes device workspace of at least dpd_backward_ws_size() bytes
  * Deterministic: the same inputs give bitwise the same gradients.  Rows start
- * from zero history. */
+ * from zero history.  dE/dcoeffs is summed in FP32 over at most 128 samples
+ * per lane, then in FP64, so its accuracy does not degrade with rows * n (any
+ * size that fits in memory, 64-bit indices throughout). */
 dpd_status dpd_backward_ws_size(const dpd_plan *plan, int64_t rows, int64_t n, size_t *bytes);
 dpd_status dpd_backward(dpd_plan *plan, void *stream, const void *coeffs_dev, const void *x,
                         const void *grad_z, void *grad_x, void *grad_coeffs, int64_t rows,
@@ -253,8 +255,9 @@ dpd_status dpd_batch_destroy(dpd_batch *batch);
  * samples (y: PA output, x: the original input, scale: 1/PA gain), written as
  * one float to *loss_dev (device; may be NULL), and dE/dRe y + j dE/dIm y =
  * (2 scale / n)(scale*y - x) written to grad_y (device, n complex64; may be
- * NULL).  Deterministic (fixed-order FP64 sum of per-block partials).  ws: device
- * workspace of dpd_loss_ws_size() bytes, owned by the caller. */
+ * NULL).  Deterministic (each thread sums in FP32 over at most 32 steps, then
+ * in FP64; fixed-order FP64 sum of per-block partials).  ws: device workspace
+ * of dpd_loss_ws_size() bytes, owned by the caller. */
 dpd_status dpd_loss_ws_size(int64_t n, size_t *bytes);
 dpd_status dpd_loss_grad(void *stream, const void *y, const void *x, int64_t n, float scale,
                          float *loss_dev, void *grad_y, void *ws, size_t ws_bytes);
