@@ -734,6 +734,7 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
             losses.append(loss.clone())
             ms.append((e0, e1))
         torch.cuda.synchronize()
+        run.total_ms = ms[0][0].elapsed_time(ms[-1][1])   # first step's start to the last one's end
         ms = [a.elapsed_time(b) for a, b in ms]
         return ms, [float(v.item()) for v in losses]
 
@@ -762,8 +763,27 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
     settle()
     trf = FusedTrainer(xd, orders, orders, L, h0)
     fused_ms, fused_loss = run(trf, steps)
+    fused_b2b_ms = run.total_ms / steps
     h_fused = trf.coeffs.cpu().numpy()
     del trf
+    # the same steps replayed from a graph: 20 captured dpd_learn_step_dev
+    # calls (Adam's step count on the device), replayed steps / 20 times
+    settle()
+    trg = FusedTrainer(xd, orders, orders, L, h0, device_step=True)
+    gph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gph):
+        for _ in range(20):
+            trg.step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps // 20):
+        gph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / (steps // 20 * 20)
+    graph_dev = float(np.max(np.abs(trg.coeffs.cpu().numpy() - h_fused)))
+    del trg, gph
     settle()
     stage_ms, stage_loss = run(FusedTrainer(xd, orders, orders, L, h0, fused_transmitter=False), 50)
     settle()
@@ -823,6 +843,9 @@ def leg_config5(torch, dpd, signals, steps=200, plain_steps=20):
     return {"workload": "64x2^18 OFDM-like, DPD {1,3,5,7} main+conj L=6, synthetic PA, Adam 1e-3",
             "accuracy_step0": acc, "suppression": sup,
             "grad_step_ms_fused": round(med(fused_ms), 4),
+            "grad_step_ms_fused_back_to_back": round(fused_b2b_ms, 4),
+            "grad_step_ms_graph_replay": round(graph_ms, 4),
+            "graph_vs_eager_coeffs_max_abs_after_%d_steps" % steps: float("%.3g" % graph_dev),
             "grad_step_roofline": _learn_roofline(rows * n, med(fused_ms), orders, L),
             "grad_step_ms_fused_transmitter_per_stage": round(med(stage_ms), 4),
             "per_stage_vs_fused_loss_rel_max_first_50": float("%.3g" % float(np.max(

@@ -364,6 +364,19 @@ dpd_status dpd_learn_step(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, voi
                           float eps, const void *x, void *z, void *grad_y, int64_t rows, int64_t n, int64_t ld,
                           float scale, float *loss_dev, void *grad_coeffs, void *ws, size_t ws_bytes);
 
+/* dpd_learn_step_dev -- dpd_learn_step with Adam's step count in device
+ * memory, for learning loops captured into a graph: *step_dev (one int32,
+ * 4-byte aligned, 0 before the first step) is advanced by one on the device,
+ * in stream order, before the update uses it, so every replay of a captured
+ * call takes the next step.  The bias corrections 1 - beta^t are computed on
+ * the device in FP64 (dpd_learn_step computes them on the host: results can
+ * differ from it in the last bit).  step_dev must not overlap the other
+ * buffers; NULL is DPD_EINVAL.  Otherwise as dpd_learn_step. */
+dpd_status dpd_learn_step_dev(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream, void *coeffs_dev,
+                              float *adam_m, float *adam_v, int32_t *step_dev, float lr, float beta1, float beta2,
+                              float eps, const void *x, void *z, void *grad_y, int64_t rows, int64_t n, int64_t ld,
+                              float scale, float *loss_dev, void *grad_coeffs, void *ws, size_t ws_bytes);
+
 /* ------------------------------------------------------- least squares --
  * The paper's coefficient estimate (section 2.2, Eq. 2): with the plan's
  * basis, row m of Psi is

@@ -45,6 +45,7 @@ struct TbParams {
     float2 *gz;               // dE/dz out (nullptr: not written)
     float *partials;          // [gridDim.x][4 L NI + 2]
     int64_t rows, n, ld, tpr; // tpr = n / chunk
+    int32_t *step;            // learning-step counter advanced by one (nullptr: none)
 };
 
 template <int NI, int L>
@@ -238,6 +239,8 @@ __global__ void __launch_bounds__(kBlock) transmit_bwd_kernel(TbParams p)
     const int64_t per = (total + nw - 1) / nw;
     const int64_t c_begin = gw * per < total ? gw * per : total;
     const int64_t c_end = c_begin + per < total ? c_begin + per : total;
+    // the learning step's counter (read by the finalisation launch after this one)
+    if (p.step != nullptr && blockIdx.x == 0 && tid == 0) *p.step += 1;
     if (c_begin < c_end) {
         // the run's last chunk first
         int64_t row = (c_end - 1) / p.tpr;
@@ -326,13 +329,20 @@ static int tb_occupancy(int NI, int L)
 
 // The one-pass backward into coefficient-gradient partials; *nblk receives
 // how many blocks wrote them.  Shapes already checked (whole chunks, aligned).
+__global__ void step_advance(int32_t *step) { *step += 1; }
+
 static hipError_t launch_tb(const dpd_plan *P, const dpd_plan *A, const dpd_plan *B, hipStream_t hs, const void *x,
                             const void *z, const void *grad_y, void *grad_z, float *partials, int64_t rows,
-                            int64_t n, int64_t rs, int *nblk)
+                            int64_t n, int64_t rs, int *nblk, int32_t *step = nullptr)
 {
     *nblk = 0;
-    if (rows * n == 0) return hipSuccess;
+    if (rows * n == 0) {
+        if (step == nullptr) return hipSuccess;
+        hipLaunchKernelGGL(step_advance, dim3(1), dim3(1), 0, hs, step);
+        return hipGetLastError();
+    }
     TbParams p;
+    p.step = step;
     p.A = A->d_table;
     p.B = B->d_table;
     p.x = (const float2 *)x;
@@ -374,9 +384,16 @@ __global__ void __launch_bounds__(kBlock) learn_finalize(const float *__restrict
                                                          float *__restrict__ loss, float2 *__restrict__ gcoef,
                                                          float *__restrict__ params, float *__restrict__ m,
                                                          float *__restrict__ v, float lr, float b1, float b2,
-                                                         float eps, float bc1, float bc2)
+                                                         float eps, float bc1, float bc2,
+                                                         const int32_t *__restrict__ step)
 {
     __shared__ double red[kBlock / 64][4];
+    if (step != nullptr) {
+        // Adam's bias corrections from the device-side step count
+        const double t = (double)*step;
+        bc1 = (float)(1.0 - pow((double)b1, t));
+        bc2 = (float)(1.0 - pow((double)b2, t));
+    }
     __shared__ double lred[kBlock / 64];
     const int q = blockIdx.x;
     if (q == map.L * map.NI + 1) {
@@ -454,15 +471,17 @@ DPD_EXPORT dpd_status dpd_learn_step_ws_size(const dpd_plan *P, size_t *bytes)
     return DPD_OK;
 }
 
-DPD_EXPORT dpd_status dpd_learn_step(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream,
-                                     void *coeffs_dev, float *adam_m, float *adam_v, int32_t step, float lr,
-                                     float beta1, float beta2, float eps, const void *x, void *z, void *grad_y,
-                                     int64_t rows, int64_t n, int64_t ld, float scale, float *loss_dev,
-                                     void *grad_coeffs, void *ws, size_t ws_bytes)
+// The learning step with the Adam step count from the host (step >= 1) or,
+// with step_dev, from a device counter the call advances.
+static dpd_status learn_step(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream, void *coeffs_dev,
+                             float *adam_m, float *adam_v, int32_t step, int32_t *step_dev, float lr, float beta1,
+                             float beta2, float eps, const void *x, void *z, void *grad_y, int64_t rows, int64_t n,
+                             int64_t ld, float scale, float *loss_dev, void *grad_coeffs, void *ws, size_t ws_bytes)
 {
     dpd_status st = check_transmit_forward(P, A, B, x, z, grad_y, rows, n, ld, scale);
     if (st != DPD_OK) return st;
-    if (coeffs_dev == nullptr || adam_m == nullptr || adam_v == nullptr || step < 1) return DPD_EINVAL;
+    if (coeffs_dev == nullptr || adam_m == nullptr || adam_v == nullptr) return DPD_EINVAL;
+    if (step_dev == nullptr ? step < 1 : (uintptr_t)step_dev % 4 != 0) return DPD_EINVAL;
     if ((uintptr_t)coeffs_dev % 8 != 0 || (uintptr_t)adam_m % 4 != 0 || (uintptr_t)adam_v % 4 != 0 ||
         (uintptr_t)grad_coeffs % 8 != 0)
         return DPD_EINVAL;
@@ -479,6 +498,15 @@ DPD_EXPORT dpd_status dpd_learn_step(dpd_plan *P, const dpd_plan *A, const dpd_p
     if (lap(coeffs_dev, adam_m) || lap(coeffs_dev, adam_v) || lap(adam_m, adam_v) || lap(grad_coeffs, coeffs_dev) ||
         lap(grad_coeffs, adam_m) || lap(grad_coeffs, adam_v))
         return DPD_EINVAL;
+    if (step_dev != nullptr) {
+        // nor the step counter any of them
+        const auto in = [kb](const void *base, const void *q) {
+            const uintptr_t u = (uintptr_t)base, v = (uintptr_t)q;
+            return base != nullptr && v + sizeof(int32_t) > u && v < u + kb;
+        };
+        if (in(coeffs_dev, step_dev) || in(adam_m, step_dev) || in(adam_v, step_dev) || in(grad_coeffs, step_dev))
+            return DPD_EINVAL;
+    }
     const int64_t rs = rows > 1 ? ld : n;
     if (!tb_shapes_ok(P, A, B, x, z, grad_y, nullptr, n, rs)) return DPD_EUNSUPPORTED;
     const hipStream_t hs = (hipStream_t)stream;
@@ -488,13 +516,35 @@ DPD_EXPORT dpd_status dpd_learn_step(dpd_plan *P, const dpd_plan *A, const dpd_p
     int nloss = 0, nblk = 0;
     hipError_t e = launch_transmit_forward(P, A, B, hs, coeffs_dev, x, z, grad_y, rows, n, ld, scale, lp, &nloss);
     if (e != hipSuccess) return hip_fail(e);
-    e = launch_tb(P, A, B, hs, x, z, grad_y, nullptr, dc, rows, n, rs, &nblk);
+    e = launch_tb(P, A, B, hs, x, z, grad_y, nullptr, dc, rows, n, rs, &nblk, step_dev);
     if (e != hipSuccess) return hip_fail(e);
-    const float bc1 = (float)(1.0 - std::pow((double)beta1, step));
-    const float bc2 = (float)(1.0 - std::pow((double)beta2, step));
+    const float bc1 = step_dev ? 0.f : (float)(1.0 - std::pow((double)beta1, step));
+    const float bc2 = step_dev ? 0.f : (float)(1.0 - std::pow((double)beta2, step));
     hipLaunchKernelGGL(learn_finalize, dim3((uint32_t)(P->map.L * P->map.NI + 2)), dim3(kBlock), 0, hs, dc, nblk,
                        P->map, lp, nloss, N > 0 ? 1.0 / (double)N : 0.0, loss_dev, (float2 *)grad_coeffs,
-                       (float *)coeffs_dev, adam_m, adam_v, lr, beta1, beta2, eps, bc1, bc2);
+                       (float *)coeffs_dev, adam_m, adam_v, lr, beta1, beta2, eps, bc1, bc2,
+                       (const int32_t *)step_dev);
     e = hipGetLastError();
     return e == hipSuccess ? DPD_OK : hip_fail(e);
+}
+
+DPD_EXPORT dpd_status dpd_learn_step(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream,
+                                     void *coeffs_dev, float *adam_m, float *adam_v, int32_t step, float lr,
+                                     float beta1, float beta2, float eps, const void *x, void *z, void *grad_y,
+                                     int64_t rows, int64_t n, int64_t ld, float scale, float *loss_dev,
+                                     void *grad_coeffs, void *ws, size_t ws_bytes)
+{
+    return learn_step(P, A, B, stream, coeffs_dev, adam_m, adam_v, step, nullptr, lr, beta1, beta2, eps, x, z,
+                      grad_y, rows, n, ld, scale, loss_dev, grad_coeffs, ws, ws_bytes);
+}
+
+DPD_EXPORT dpd_status dpd_learn_step_dev(dpd_plan *P, const dpd_plan *A, const dpd_plan *B, void *stream,
+                                         void *coeffs_dev, float *adam_m, float *adam_v, int32_t *step_dev, float lr,
+                                         float beta1, float beta2, float eps, const void *x, void *z, void *grad_y,
+                                         int64_t rows, int64_t n, int64_t ld, float scale, float *loss_dev,
+                                         void *grad_coeffs, void *ws, size_t ws_bytes)
+{
+    if (step_dev == nullptr) return DPD_EINVAL;
+    return learn_step(P, A, B, stream, coeffs_dev, adam_m, adam_v, 0, step_dev, lr, beta1, beta2, eps, x, z, grad_y,
+                      rows, n, ld, scale, loss_dev, grad_coeffs, ws, ws_bytes);
 }

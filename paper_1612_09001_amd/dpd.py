@@ -84,6 +84,9 @@ _SIGS = {
     "dpd_learn_step": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                        ctypes.c_float, _vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, _vp, _vp, _vp,
                        ctypes.c_size_t],
+    "dpd_learn_step_dev": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, _vp, _vp, _vp, _i64, _i64, _i64, ctypes.c_float, _vp, _vp, _vp,
+                           ctypes.c_size_t],
     "dpd_adam_step": [_vp, _vp, _vp, _vp, _vp, _i64, _i32, ctypes.c_float, ctypes.c_float,
                       ctypes.c_float, ctypes.c_float],
     "dpd_ls_ws_size": [_vp, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
@@ -317,6 +320,14 @@ def dpd_learn_step(plan_p, plan_a, plan_b, stream, coeffs_ptr, m_ptr, v_ptr, ste
     _check(lib().dpd_learn_step(plan_p, plan_a, plan_b, stream, coeffs_ptr, m_ptr, v_ptr, int(step), float(lr),
                                 float(beta1), float(beta2), float(eps), x_ptr, z_ptr, gy_ptr, int(rows), int(n),
                                 int(ld), float(scale), loss_ptr, gc_ptr, ws_ptr, int(ws_bytes)), "dpd_learn_step")
+
+
+def dpd_learn_step_dev(plan_p, plan_a, plan_b, stream, coeffs_ptr, m_ptr, v_ptr, step_ptr, lr, beta1, beta2, eps,
+                       x_ptr, z_ptr, gy_ptr, rows, n, ld, scale, loss_ptr, gc_ptr, ws_ptr, ws_bytes):
+    _check(lib().dpd_learn_step_dev(plan_p, plan_a, plan_b, stream, coeffs_ptr, m_ptr, v_ptr, step_ptr, float(lr),
+                                    float(beta1), float(beta2), float(eps), x_ptr, z_ptr, gy_ptr, int(rows), int(n),
+                                    int(ld), float(scale), loss_ptr, gc_ptr, ws_ptr, int(ws_bytes)),
+           "dpd_learn_step_dev")
 
 
 def dpd_adam_step(stream, p_ptr, g_ptr, m_ptr, v_ptr, count, step, lr, beta1=0.9, beta2=0.999,

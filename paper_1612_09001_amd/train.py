@@ -15,6 +15,10 @@ is one library call, ``dpd_learn_step`` (three launches):
   finalisation + Adam        loss and gradient summed in FP64, Adam applied
                              to the K complex coefficients in place
 
+With ``device_step=True`` the call is ``dpd_learn_step_dev``: Adam's step
+count lives on the device and the call advances it, so ``step()`` can be
+captured into a HIP graph and replayed (every replay takes the next step).
+
 Other row lengths run the same passes as separate calls
 (dpd_transmit_loss_grad, dpd_transmit_backward through a dE/dz buffer,
 dpd_adam_step).  ``one_pass=False`` runs the predistorter as its own launch
@@ -39,7 +43,7 @@ from .pa import SyntheticPA, iq_coeffs, pa_coeffs
 
 class FusedTrainer:
     def __init__(self, x, main_orders, conj_orders, L, coeffs0, lr=1e-3, betas=(0.9, 0.999),
-                 eps=1e-8, fused_transmitter=True, one_pass=True):
+                 eps=1e-8, fused_transmitter=True, one_pass=True, device_step=False):
         if x.dim() != 2 or not x.is_contiguous():
             raise ValueError("x must be a contiguous (rows, n) complex64 GPU tensor")
         self.x = x
@@ -73,6 +77,12 @@ class FusedTrainer:
         # (whole 256-sample chunks; torch's allocations are 16-byte aligned)
         self.one_call = self.one_pass and self.n % 256 == 0
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        # Adam's step count on the device (advanced by each call), for graph capture
+        self.step_dev = None
+        if device_step:
+            if not (self.fused_transmitter and self.one_call):
+                raise ValueError("device_step needs the one-call step (one-pass shapes, n a multiple of 256)")
+            self.step_dev = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def step(self):
         """One gradient step; returns the loss of the coefficients before it
@@ -81,6 +91,13 @@ class FusedTrainer:
         R, N, ld = self.rows, self.n, self.n
         P = lambda t: t.data_ptr()
         iq, pa = self.pa.iq.handle, self.pa.pa.handle
+        if self.step_dev is not None:
+            self.t += 1
+            _dpd.dpd_learn_step_dev(self.plan.handle, iq, pa, st, P(self.coeffs), P(self.m), P(self.v),
+                                    P(self.step_dev), self.lr, self.betas[0], self.betas[1], self.eps, P(self.x),
+                                    P(self.z), P(self.gy), R, N, ld, 1.0 / self.pa.gain, P(self.loss), P(self.gc),
+                                    P(self.ws), self.ws_bytes)
+            return self.loss
         if self.fused_transmitter and self.one_call:
             self.t += 1
             _dpd.dpd_learn_step(self.plan.handle, iq, pa, st, P(self.coeffs), P(self.m), P(self.v), self.t, self.lr,
@@ -119,13 +136,16 @@ class FusedTrainer:
         return self.loss
 
     def state_dict(self):
-        return {"coeffs": self.coeffs.clone(), "m": self.m.clone(), "v": self.v.clone(), "t": self.t}
+        t = int(self.step_dev.item()) if self.step_dev is not None else self.t
+        return {"coeffs": self.coeffs.clone(), "m": self.m.clone(), "v": self.v.clone(), "t": t}
 
     def load_state_dict(self, d):
         self.coeffs.copy_(d["coeffs"])
         self.m.copy_(d["m"])
         self.v.copy_(d["v"])
         self.t = int(d["t"])
+        if self.step_dev is not None:
+            self.step_dev.fill_(self.t)
 
 
 class AutogradTrainer:

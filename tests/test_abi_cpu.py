@@ -133,4 +133,9 @@ def test_learning_entry_points_reject_on_the_host(lib):
     assert lib.dpd_learn_step(None, None, None, None, fake, fake, fake, 1, ctypes.c_float(1e-3),
                               ctypes.c_float(0.9), ctypes.c_float(0.999), ctypes.c_float(1e-8), fake, fake, fake,
                               1, 256, 256, ctypes.c_float(0.1), None, None, fake, 1 << 20) == dpd.DPD_EINVAL
+    for step_dev in (None, ctypes.c_void_p((1 << 20) + 2)):   # missing, misaligned
+        assert lib.dpd_learn_step_dev(None, None, None, None, fake, fake, fake, step_dev, ctypes.c_float(1e-3),
+                                      ctypes.c_float(0.9), ctypes.c_float(0.999), ctypes.c_float(1e-8), fake, fake,
+                                      fake, 1, 256, 256, ctypes.c_float(0.1), None, None, fake,
+                                      1 << 20) == dpd.DPD_EINVAL
     assert lib.dpd_set_coeffs_async(None, None, None) == dpd.DPD_EINVAL

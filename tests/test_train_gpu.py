@@ -277,3 +277,35 @@ def test_learn_step_arguments(torch):
             call(**kw)
         assert e.value.status == status, kw
     torch.cuda.synchronize()
+
+
+def test_learn_step_graph_replay(torch):
+    """dpd_learn_step_dev captured once into a graph and replayed: each replay
+    takes the next Adam step (the device counter advances), bitwise equal to
+    eager calls of the same entry point; within FP32 rounding of
+    dpd_learn_step, which computes the bias corrections on the host."""
+    from paper_1612_09001_amd.train import FusedTrainer
+
+    x, xd = _data(torch, 4, 1 << 14, cid=61)
+    h = signals.aph_coeffs(*ORDERS, L, config_id=61)
+    warm = FusedTrainer(xd, *ORDERS, L, h, lr=1e-3, device_step=True)
+    warm.step()   # first-use set-up of the library outside the capture
+    torch.cuda.synchronize()
+    graphed = FusedTrainer(xd, *ORDERS, L, h, lr=1e-3, device_step=True)
+    eager = FusedTrainer(xd, *ORDERS, L, h, lr=1e-3, device_step=True)
+    host = FusedTrainer(xd, *ORDERS, L, h, lr=1e-3)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        graphed.step()
+    torch.cuda.synchronize()
+    assert int(graphed.step_dev.item()) == 0   # capturing runs nothing
+    for r in range(6):
+        g.replay()
+        eager.step()
+        host.step()
+        torch.cuda.synchronize()
+        assert int(graphed.step_dev.item()) == r + 1
+        for key in ("coeffs", "m", "v", "loss", "gc"):
+            assert torch.equal(getattr(graphed, key), getattr(eager, key)), (r, key)
+        assert torch.allclose(graphed.coeffs, host.coeffs, rtol=0, atol=1e-6), r
+        assert torch.allclose(graphed.loss, host.loss, rtol=1e-6, atol=0), r
