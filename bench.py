@@ -504,8 +504,8 @@ def leg_table2(torch, dpd, signals, steps=200):
 
 def leg_ingest(torch, dpd, signals, reps=3):
     """Host ingestion: 2^25 samples from pinned host memory through the
-    headline predistorter back to pinned host memory (chunks of 2^22 on two
-    streams, copies overlapped with filtering), and the zero-copy form (one
+    headline predistorter back to pinned host memory (chunks of 2^20 to 2^22
+    on three streams, copies overlapped with filtering), and the zero-copy form (one
     launch on the buffers' device mappings); host-link-bound rates, never the
     headline value."""
     from paper_1612_09001_amd import ingest
@@ -515,8 +515,8 @@ def leg_ingest(torch, dpd, signals, reps=3):
     xh = torch.from_numpy(signals.ofdm_16qam(n, config_id=1)).pin_memory()
     zh = torch.empty(n, dtype=torch.complex64).pin_memory()
     out = {"workload": "pinned host -> predistorter (headline basis) -> pinned host, 2^25 samples"}
-    for chunk in (1 << 20, 1 << 22):
-        pipe = ingest.HostPipeline(plan, chunk=chunk)
+    for chunk in (1 << 20, 1 << 21, 1 << 22):
+        pipe = ingest.HostPipeline(plan, chunk=chunk, nbuf=3)
         pipe.run(xh, zh)
         ts = []
         for _ in range(reps):
@@ -530,15 +530,15 @@ def leg_ingest(torch, dpd, signals, reps=3):
             "host_link_gbs_each_way": round(8 * n / t / 1e9, 2)}
         del pipe
     # the same copies with no filtering (the host-link ceiling of this pattern)
-    chunk = 1 << 22
-    ss = [torch.cuda.Stream(), torch.cuda.Stream()]
+    chunk = 1 << 21
+    ss = [torch.cuda.Stream() for _ in range(3)]
     bufs = [torch.empty(chunk, dtype=torch.complex64, device="cuda") for _ in ss]
 
     def copies():
         for i, t0 in enumerate(range(0, n, chunk)):
-            with torch.cuda.stream(ss[i % 2]):
-                bufs[i % 2].copy_(xh[t0:t0 + chunk], non_blocking=True)
-                zh[t0:t0 + chunk].copy_(bufs[i % 2], non_blocking=True)
+            with torch.cuda.stream(ss[i % 3]):
+                bufs[i % 3].copy_(xh[t0:t0 + chunk], non_blocking=True)
+                zh[t0:t0 + chunk].copy_(bufs[i % 3], non_blocking=True)
         for q in ss:
             q.synchronize()
 
@@ -549,7 +549,7 @@ def leg_ingest(torch, dpd, signals, reps=3):
         copies()
         ts.append(time.perf_counter() - t0)
     t = float(np.median(ts))
-    out["copies_only_chunk_2^22"] = {"ms": round(t * 1e3, 2), "host_link_gbs_each_way": round(8 * n / t / 1e9, 2)}
+    out["copies_only_chunk_2^21"] = {"ms": round(t * 1e3, 2), "host_link_gbs_each_way": round(8 * n / t / 1e9, 2)}
     # zero copy: one launch that reads and writes the pinned buffers in place
     zc = ingest.ZeroCopy(plan)
     zc.run(xh, zh)
@@ -563,7 +563,7 @@ def leg_ingest(torch, dpd, signals, reps=3):
                         "host_link_gbs_each_way": round(8 * n / t / 1e9, 2)}
     ref = _oracle().forward(xh.numpy(), orders, orders, L, signals.aph_coeffs(orders, orders, L, config_id=1))
     out["accuracy_zero_copy"] = gate(zh.numpy(), ref)
-    pipe = ingest.HostPipeline(plan, chunk=1 << 22)
+    pipe = ingest.HostPipeline(plan)
     zh.fill_(0)
     pipe.run(xh, zh)
     out["accuracy_pipeline"] = gate(zh.numpy(), ref)
