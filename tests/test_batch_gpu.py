@@ -77,6 +77,27 @@ def test_small_batch_matches_oracle_and_each(torch, mods, orc, S):
     b.close()
 
 
+def test_many_short_streams(torch, mods, orc):
+    """3000 streams of seeded random length 0..3000 (mostly ragged chunks), P_max
+    1..11 and L 1..10 (classes outside the persistent kernel's included): every
+    output against the oracle and bitwise against the per-stream launches, at
+    the default launch shape (whole slots of blocks: the heavy/light split)."""
+    dpd, batch = mods
+    rng = np.random.default_rng(2024)
+    specs = [(int(rng.integers(0, 3001)), int(rng.choice([1, 3, 5, 7, 9, 11])), int(rng.integers(1, 11)))
+             for _ in range(3000)]
+    wl = batch.BatchWorkload(specs, config_id=72)
+    b = batch.Batch(wl.streams())
+    wl.z.fill_(complex(7.0, -7.0))
+    b.apply()
+    z1 = wl.z.cpu().numpy()
+    _check_streams(wl, z1, orc)
+    wl.z.fill_(complex(7.0, -7.0))
+    b.apply_each()
+    assert np.array_equal(z1, wl.z.cpu().numpy()), "persistent batch differs from per-stream launches"
+    b.close()
+
+
 def _written(wl, z):
     """Concatenation of the stream regions (the padding between is never written)."""
     return np.concatenate([z[o:o + n] for o, (n, _, _) in zip(wl.offsets, wl.specs)])
