@@ -1,8 +1,8 @@
 """More than 2^31 samples in one call (64-bit indexing in every kernel, sums
 whose rounding error must not grow with the length): the forward and the
 backward of the headline basis on one stream of N = 2^31 + 2^20 + 777
-samples, and one learning step over 8193 rows of 2^18, against the FP64
-oracle.  The stream and its output gradient repeat seeded blocks of P = 2^20
+samples, one batch launch over 2^31 + 2^20 + 8 samples in three streams,
+and one learning step over 8193 rows of 2^18, against the FP64 oracle.  The stream and its output gradient repeat seeded blocks of P = 2^20
 samples, so the oracle gets each sampled output from the L-sample window it
 depends on, and the whole coefficient gradient from three runs over one
 block: the first block (zero history), one later block (the block's own end
@@ -122,3 +122,36 @@ def test_learning_step_past_2_31(torch, orc):
     E, g = opa.chain_loss_and_gradient(orc, row[None, :], (orders, orders), Lt, h)
     assert abs(loss - E) <= 1e-5 * E, (loss, E)
     assert_dcoef(gc, g, "chain gradient, 8193 x 2^18", entry_max=1e-4, rel_max=1e-4)
+
+
+def test_batch_past_2_31(torch, dpd, orc):
+    """One persistent batch launch over 2^31 + 2^20 + 8 samples in three
+    streams, each repeating its own seeded 2^20-sample block (P_max 9 and L 8,
+    P_max 5 and L 3, P_max 7 and L 6): sampled outputs of every stream against
+    the oracle."""
+    from paper_1612_09001_amd import batch
+
+    specs = [((1 << 30) + 5, 9, 8), ((1 << 29) + 3, 5, 3), ((1 << 29) + (1 << 20), 7, 6)]
+    rng = np.random.default_rng(7)
+    streams, checks = [], []
+    for s, (n, pmax, Ls) in enumerate(specs):
+        orders = signals.odd_orders(pmax)
+        blk = signals.ofdm_16qam(P, config_id=30 + s).astype(np.complex64)
+        h = signals.aph_coeffs(orders, orders, Ls, config_id=30 + s)
+        x = torch.from_numpy(blk).cuda().repeat(n // P + 1)[:n]
+        z = torch.empty(n, dtype=torch.complex64, device="cuda")
+        streams.append({"in": x, "out": z, "n": n, "main_orders": orders, "conj_orders": orders, "L": Ls,
+                        "coeffs": torch.from_numpy(h.astype(np.complex64)).cuda()})
+        edges = np.concatenate([np.arange(0, 8), np.arange(P - 8, P + 8), np.arange(n - 16, n),
+                                rng.integers(0, n, 2048)])
+        checks.append((np.unique(edges[(edges >= 0) & (edges < n)]), blk, orders, Ls, h))
+    b = batch.Batch(streams)
+    b.apply()
+    for s, (idx, blk, orders, Ls, h) in enumerate(checks):
+        got = streams[s]["out"][torch.from_numpy(idx).cuda()].cpu().numpy()
+        pos = idx[:, None] + (np.arange(Ls) - (Ls - 1))[None, :]
+        w = blk[np.mod(pos, P)]
+        w[pos < 0] = 0
+        ref = orc.forward_at(w.reshape(-1), orders, orders, Ls, h, np.arange(idx.size) * Ls + Ls - 1)
+        assert_parity(got, ref, "batch stream %d past 2^31 samples in all" % s)
+    b.close()
