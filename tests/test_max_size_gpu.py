@@ -2,7 +2,8 @@
 whose rounding error must not grow with the length): the forward and the
 backward of the headline basis on one stream of N = 2^31 + 2^20 + 777
 samples, one batch launch over 2^31 + 2^20 + 8 samples in three streams,
-and one learning step over 8193 rows of 2^18, against the FP64 oracle.  The stream and its output gradient repeat seeded blocks of P = 2^20
+the least-squares normal equations over the same long stream, and one
+learning step over 8193 rows of 2^18, against the FP64 oracle.  The stream and its output gradient repeat seeded blocks of P = 2^20
 samples, so the oracle gets each sampled output from the L-sample window it
 depends on, and the whole coefficient gradient from three runs over one
 block: the first block (zero history), one later block (the block's own end
@@ -12,7 +13,7 @@ are those of that row."""
 import numpy as np
 import pytest
 
-from metrics import assert_dcoef, assert_parity
+from metrics import LS_REL_MAX, assert_dcoef, assert_parity, ls_errors
 from paper_1612_09001_amd import signals
 
 pytestmark = pytest.mark.gpu
@@ -155,3 +156,39 @@ def test_batch_past_2_31(torch, dpd, orc):
         ref = orc.forward_at(w.reshape(-1), orders, orders, Ls, h, np.arange(idx.size) * Ls + Ls - 1)
         assert_parity(got, ref, "batch stream %d past 2^31 samples in all" % s)
     b.close()
+
+
+def test_ls_normal_past_2_31(torch, dpd, orc):
+    """The normal equations of the headline basis over N = 2^31 + 2^20 + 777
+    samples (input and target repeat seeded 2^20-sample blocks): every entry
+    of A and b against the FP64 oracle, composed from the first block, one
+    later block (its rows with the block's own end as history: the oracle's
+    sums over the history followed by the block, less those over the history
+    alone, whose target is zero) and the ragged end."""
+    y_blk = signals.ofdm_16qam(P, config_id=31, stream_id=7).astype(np.complex64)
+    t_blk = (0.5 * signals.ofdm_16qam(P, config_id=32, stream_id=7)).astype(np.complex64)
+    plan = dpd.Plan(MO, CO, L, signals.aph_coeffs(MO, CO, L, config_id=3))
+    y, t = _repeat(torch, y_blk), _repeat(torch, t_blk)
+    A, b = plan.ls_normal(y, t)
+    A, b = A.cpu().numpy(), b.cpu().numpy()
+    del y, t
+    hist = y_blk[P - (L - 1):]
+    zh = np.zeros(L - 1, np.complex64)
+    R = N % P
+
+    def with_hist(yy, tt):
+        a1, b1 = orc.ls_normal(np.concatenate([hist, yy]), MO, CO, L, np.concatenate([zh, tt]))
+        a0, b0 = orc.ls_normal(hist, MO, CO, L, zh)
+        return a1 - a0, b1 - b0
+
+    a_first, b_first = orc.ls_normal(y_blk, MO, CO, L, t_blk)
+    a_later, b_later = with_hist(y_blk, t_blk)
+    a_end, b_end = with_hist(y_blk[:R], t_blk[:R])
+    m = N // P
+    Ar = a_first + (m - 1) * a_later + a_end
+    br = b_first + (m - 1) * b_later + b_end
+    t2 = m * float(np.sum(np.abs(t_blk.astype(np.complex128)) ** 2)) + float(
+        np.sum(np.abs(t_blk[:R].astype(np.complex128)) ** 2))
+    ea, eb, ma, mb = ls_errors(A, b, Ar, br, t2)
+    assert max(ea, eb, ma, mb) <= LS_REL_MAX, "A frob %.3g, b frob %.3g, A entry %.3g, b entry %.3g" % (
+        ea, eb, ma, mb)
