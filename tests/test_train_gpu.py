@@ -276,6 +276,21 @@ def test_learn_step_arguments(torch):
         with pytest.raises(dpd.DPDError) as e:
             call(**kw)
         assert e.value.status == status, kw
+    # the device-counter form: the counter may not overlap the coefficients or
+    # the moments, and must be 4-byte aligned
+    cnt = torch.zeros(2, dtype=torch.int32, device="cuda")
+
+    def call_dev(sp):
+        dpd.dpd_learn_step_dev(P.handle, pa.iq.handle, pa.pa.handle, st, ptr(c), ptr(m), ptr(v), sp, 1e-3, 0.9,
+                               0.999, 1e-8, ptr(xd), ptr(z), ptr(gy), rows, n, n, 0.1, 0, 0, ptr(ws), wsb)
+
+    call_dev(ptr(cnt))
+    torch.cuda.synchronize()
+    assert int(cnt[0].item()) == 1 and int(cnt[1].item()) == 0
+    for sp in (ptr(c) + 8, ptr(m), ptr(v) + 4, ptr(cnt) + 2):
+        with pytest.raises(dpd.DPDError) as e:
+            call_dev(sp)
+        assert e.value.status == dpd.DPD_EINVAL, sp
     torch.cuda.synchronize()
 
 
